@@ -1,0 +1,101 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/adaptomp.h"
+
+namespace ao {
+
+// Thread-local error message (ao_last_error).
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+// Launch one Jacobi sweep dst <- J(src) of a GPU variant on `s`.  Checks the
+// launch shape on the host first and returns hipErrorInvalidConfiguration
+// without launching when it does not fit the kernel.
+hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst, int nx, int ny,
+                            int nz, hipStream_t s);
+
+// Host (OpenMP) variant: S sweeps from u0 into out using tmp (N doubles) as
+// the second ping-pong buffer.  All three are host memory.
+void jacobi_host_sweeps(const ao_variant& v, const double* u0, double* out, double* tmp, int nx,
+                        int ny, int nz, int sweeps);
+
+// SpMV: per-matrix plan (features, merge-path partition) built on the GPU.
+struct SpmvPlan {
+    const int32_t* row_ptr = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    float features[AO_MAX_FEATURES] = {0};
+    bool have_features = false;
+    int32_t max_len = 0;  // longest row
+    // merge-path partition, per chunk size
+    int32_t mp_chunk = 0;
+    int32_t mp_blocks = 0;
+    int32_t* mp_start_row = nullptr;   // [mp_blocks + 1]
+    int32_t* mp_start_unit = nullptr;  // [mp_blocks + 1] unit index within the start row
+    int32_t* unit_ptr = nullptr;       // [n + 1] first 64-block unit of each row
+    double* unit_sums = nullptr;       // [units] sums of units of rows split across chunks
+    int64_t units = 0;
+    ~SpmvPlan();
+};
+
+hipError_t spmv_features(SpmvPlan& p, hipStream_t s);
+hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
+                    const double* x, double* y, hipStream_t s);
+
+// Cost model kernels.
+struct MlpNorm {
+    float mu[AO_MAX_FEATURES];
+    float sd[AO_MAX_FEATURES];
+    float y_mean;
+};
+hipError_t mlp_forward(const float* params, const float* x, int batch, float* out, hipStream_t s);
+hipError_t mlp_grad(const float* params, const float* x, const float* y, const float* mask,
+                    int batch, float* grad, float* loss, hipStream_t s);
+hipError_t mlp_adam(float* params, float* m, float* v, const float* grad, int t, float lr,
+                    hipStream_t s);
+// Whole training run in one launch: epochs over n samples (x[n*6], y[n],
+// variant id[n]) in the order perm[epochs*n]; params updated in place,
+// mv = Adam moments scratch (2 * AO_MLP_PARAMS floats, zeroed here),
+// epoch_loss[epochs] written.
+hipError_t mlp_train_launch(float* params, const float* x, const float* y, const int32_t* var,
+                            const int32_t* perm, int n, int epochs, int batch, float lr,
+                            float* mv, float* epoch_loss, hipStream_t s);
+// Batched inference: raw features feats[batch*6] -> argmin over allowed
+// variants (bit v of allowed_mask) of the predicted ln-time, and the
+// predictions pred[batch*12] (may be null).
+hipError_t mlp_select_launch(const float* params, const MlpNorm* norm, const float* feats,
+                             int batch, int num_variants, int allowed_mask, int32_t* ids,
+                             float* pred, hipStream_t s);
+
+// Batched Jacobi.
+struct BatchItem {
+    int32_t inst;        // instance index
+    int32_t tx0, ty0, tz0;  // tile origin
+};
+struct BatchInst {
+    const double* u0;
+    double* out;
+    double* tmp;
+    int32_t nx, ny, nz, sweeps;
+};
+hipError_t batch_sweep_launch(const BatchInst* insts, const BatchItem* items, int nitems,
+                              const int32_t* item_tile, int sweep, int grid, hipStream_t s);
+
+// SplitMix64 (Steele, Lea, Flood 2014): output i (1-based) of the stream
+// seeded with s is mix(s + i * gamma).
+static inline uint64_t splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static inline uint64_t splitmix_at(uint64_t seed, uint64_t i) {
+    return splitmix_mix(seed + i * 0x9E3779B97F4A7C15ull);
+}
+
+}  // namespace ao

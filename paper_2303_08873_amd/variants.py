@@ -1,0 +1,42 @@
+"""Variant tables of the region workloads (declaration order = variant id,
+as categorical variants are numbered from 0 in the order given, Sec. 3.1
+model_output clause)."""
+from __future__ import annotations
+
+from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, FAM_JACOBI_DIRECT, FAM_JACOBI_HOST,
+                   FAM_JACOBI_ZMARCH, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW,
+                   FAM_SPMV_WAVE_ROW, Variant)
+
+
+def jacobi_variants_blocks():
+    """Threads-per-block variants 64 / 256 / 1024 of the one-point-per-thread
+    Jacobi kernel (the GPU-threads use case, Sec. 3.2 / Sec. 5)."""
+    return [Variant(AO_TARGET_GPU, FAM_JACOBI_DIRECT, 64, 1, 1, 0),
+            Variant(AO_TARGET_GPU, FAM_JACOBI_DIRECT, 64, 4, 1, 0),
+            Variant(AO_TARGET_GPU, FAM_JACOBI_DIRECT, 64, 16, 1, 0)]
+
+
+# ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
+JACOBI_SWEEP_GPU = [(FAM_JACOBI_DIRECT, 32, 4, 1), (FAM_JACOBI_DIRECT, 64, 4, 1),
+                    (FAM_JACOBI_DIRECT, 64, 8, 1), (FAM_JACOBI_ZMARCH, 32, 8, 16),
+                    (FAM_JACOBI_ZMARCH, 64, 8, 64)]
+JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
+STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
+
+
+def jacobi_variants_sweep():
+    """10 variants: 5 GPU block / tile shapes (direct and LDS z-march) and 5
+    host-CPU cache-block shapes."""
+    out = [Variant(AO_TARGET_GPU, f, bx, by, bz, 0) for f, bx, by, bz in JACOBI_SWEEP_GPU]
+    out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]
+    return out
+
+
+def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64):
+    """{thread-per-row, wavefront-per-row, merge-path} x block sizes."""
+    out = []
+    for fam in (FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH):
+        for b in blocks:
+            out.append(Variant(AO_TARGET_GPU, fam, b, wave_lanes if fam == FAM_SPMV_WAVE_ROW else 0,
+                               1, 0))
+    return out

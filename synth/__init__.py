@@ -178,3 +178,38 @@ def csr_matrix(n: int, seed: int, mean: float = 16.0, tail: float = 1.5, max_len
     val = normal_values(col.size, seed)
     x = dense_vector_pm1(n, seed)
     return {"row_ptr": row_ptr, "col": col, "val": val, "x": x}
+
+
+# --------------------------------------------------------------------------
+# The same streams drawn on a torch device (int64 two's-complement wrap
+# equals the uint64 arithmetic above; right shifts are made logical).
+# --------------------------------------------------------------------------
+
+def _s64(v: int) -> int:
+    v &= _MASK64
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _lsr(z, k: int):
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def u01_torch(seed: int, count: int, device, start: int = 0):
+    """u01(seed, count, start) computed on a torch device."""
+    import torch
+    out = torch.empty(count, dtype=torch.float64, device=device)
+    g, m1, m2, s = _s64(0x9E3779B97F4A7C15), _s64(0xBF58476D1CE4E5B9), _s64(0x94D049BB133111EB), _s64(seed)
+    step = 1 << 25
+    for lo in range(0, count, step):
+        hi = min(count, lo + step)
+        z = torch.arange(start + lo + 1, start + hi + 1, dtype=torch.int64, device=device) * g + s
+        z = (z ^ _lsr(z, 30)) * m1
+        z = (z ^ _lsr(z, 27)) * m2
+        z = z ^ _lsr(z, 31)
+        out[lo:hi] = _lsr(z, 11).to(torch.float64) * (2.0 ** -53)
+    return out
+
+
+def grid_u01_torch(nx: int, ny: int, nz: int, seed: int, device):
+    """grid_u01 drawn directly in device memory (same values)."""
+    return u01_torch(seed, nx * ny * nz, device)

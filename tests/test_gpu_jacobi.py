@@ -1,0 +1,177 @@
+"""GPU parity of the Jacobi region variants against the CPU oracle, through
+the C ABI: every variant bit-identical to every other and to the oracle
+(which sums in the same order; the bound is elementwise |g-o| <= 1e-12|o|,
+met here with zero error), on ragged shapes, both residencies, edge cases,
+and the full 512^3 x 20 workload on sampled windows."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2303_08873_amd as ao
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    return ao, torch, dev, torch.cuda.current_stream(dev)
+
+
+def _check(got, want):
+    assert got.shape == want.shape
+    if not np.array_equal(got, want):
+        rel = np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300))
+        bad = int(np.sum(got != want))
+        assert rel <= 1e-12, f"{bad} elements differ, max rel {rel:g}"
+        pytest.fail(f"{bad} elements differ from the oracle (max rel {rel:g}, within 1e-12 "
+                    "but the variants promise bit identity)")
+
+
+def test_config_blocks_64cubed(env, orc):
+    # 64^3 grid, 10 sweeps, u0 ~ U[0,1) seed 1, variants 64 / 256 / 1024 threads
+    ao, torch, dev, st = env
+    n, S = 64, 10
+    u0_h = synth.grid_u01(n, n, n, seed=1)
+    want = orc.jacobi7(u0_h, n, n, n, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    h = ao.region_declare_variants("gpu_c1", ao.AO_JACOBI7_F64, ao.jacobi_variants_blocks(),
+                                   model_type="exhaustive")
+    a = ao.jacobi_args(u0, out, n, n, n, S)
+    for v in range(3):
+        out.fill_(-1.0)
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        _check(out.cpu().numpy(), want)
+    med = ao.region_profile(h, a, warmup=2, reps=5, stream=st)
+    assert all(math.isfinite(t) and t > 0 for t in med)
+    rc, chosen = ao.region_run(h, a, stream=st)   # exhaustive producer
+    torch.cuda.synchronize()
+    assert 0 <= chosen < 3
+    _check(out.cpu().numpy(), want)
+    assert torch.equal(u0.cpu(), torch.from_numpy(u0_h))  # u0 untouched
+    ao.region_destroy(h)
+
+
+SHAPES = [((37, 29, 13), 3), ((1, 1, 50), 2), ((65, 3, 7), 1), ((5, 130, 2), 4),
+          ((129, 9, 33), 2), ((64, 64, 1), 5), ((3, 3, 3), 7)]
+
+
+@pytest.mark.parametrize("shape,S", SHAPES)
+@pytest.mark.parametrize("resident", [1, 0])
+def test_sweep_variants_ragged(env, orc, shape, S, resident):
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=2000 + nx)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    if resident:
+        u0 = torch.from_numpy(u0_h).to(dev)
+        out = torch.empty_like(u0)
+    else:
+        u0 = torch.from_numpy(u0_h).pin_memory()
+        out = torch.empty(u0.shape, dtype=torch.float64).pin_memory()
+    h = ao.region_declare_variants("gpu_c2", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep(),
+                                   model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, nx, ny, nz, S, resident=resident)
+    for v in range(10):
+        out.fill_(-1.0)
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        _check(out.cpu().numpy(), want)
+
+
+def test_nontemporal_and_zmarch_shapes(env, orc):
+    ao, torch, dev, st = env
+    nx, ny, nz, S = 70, 21, 45, 3
+    u0_h = synth.grid_u01(nx, ny, nz, seed=9)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 64, 4, 1, ao.AO_VF_NT_STORE),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 64, 4, 7, ao.AO_VF_NT_STORE),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 128, 8, 1, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 16, 4, 100, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 256, 4, 1, 0)]
+    h = ao.region_declare_variants("gpu_shapes", ao.AO_JACOBI7_F64, vs, model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+    for v in range(len(vs)):
+        out.fill_(-1.0)
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        _check(out.cpu().numpy(), want)
+
+
+def test_edge_cases(env, orc):
+    ao, torch, dev, st = env
+    h = ao.region_declare_variants("gpu_edges", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep(),
+                                   model_type="roundrobin")
+    # zero sweeps: out = u0
+    u0_h = synth.grid_u01(9, 8, 7, seed=4)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    for v in (0, 3, 5):
+        out.fill_(-1.0)
+        ao.region_run(h, ao.jacobi_args(u0, out, 9, 8, 7, 0), stream=st, variant=v)
+        torch.cuda.synchronize()
+        assert torch.equal(out, u0)
+    # empty grid: nothing to do, no error
+    e = torch.empty(0, dtype=torch.float64, device=dev)
+    ao.region_run(h, ao.jacobi_args(e, e, 0, 4, 4, 3), stream=st, variant=0)
+    # launch failure: a 64x32 block (2048 threads) is refused on the host and masked
+    bad = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 64, 32, 1, 0),
+           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 64, 4, 1, 0)]
+    hb = ao.region_declare_variants("gpu_badlaunch", ao.AO_JACOBI7_F64, bad, model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, 9, 8, 7, 2)
+    with pytest.raises(ao.AdaptError) as err:
+        ao.region_run(hb, a, stream=st, variant=0)
+    assert err.value.code == -7
+    assert ao.region_stats(hb).failed_mask == 1
+    for _ in range(3):
+        rc, v = ao.region_run(hb, a, stream=st)
+        assert v == 1
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), orc.jacobi7(u0_h, 9, 8, 7, 2))
+    med = ao.region_profile(hb, a, warmup=1, reps=2, stream=st)
+    assert math.isinf(med[0]) and math.isfinite(med[1])
+
+
+def test_full_size_512_sampled_windows(env, orc):
+    # 512^3, 20 sweeps, device-resident, every GPU variant of the size sweep.
+    # The value at p after S sweeps depends only on u0 within distance S, so
+    # the oracle on the window [p-S, p+S]^3 (clipped to the grid, zero ghost
+    # layer outside) gives it exactly.
+    ao, torch, dev, st = env
+    n, S = 512, 20
+    u0 = synth.grid_u01_torch(n, n, n, seed=2009, device=dev)
+    out = torch.empty_like(u0)
+    h = ao.region_declare_variants("gpu_full", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep()[:5],
+                                   model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, n, n, n, S)
+    pts = [(0, 0, 0), (511, 511, 511), (255, 17, 300), (3, 500, 44), (511, 0, 256), (100, 200, 511)]
+    u3 = u0.view(n, n, n)
+    ref = None
+    for v in range(5):
+        out.fill_(-1.0)
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        o3 = out.view(n, n, n)
+        got = torch.stack([o3[k, j, i] for i, j, k in pts]).cpu().numpy()
+        if ref is None:
+            ref = out.clone()
+            want = []
+            for i, j, k in pts:
+                lo = [max(0, c - S) for c in (i, j, k)]
+                hi = [min(n, c + S + 1) for c in (i, j, k)]
+                win = u3[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous().cpu().numpy()
+                wz, wy, wx = win.shape
+                r = orc.jacobi7(win.reshape(-1), wx, wy, wz, S).reshape(wz, wy, wx)
+                want.append(r[k - lo[2], j - lo[1], i - lo[0]])
+            assert np.array_equal(got, np.array(want))
+        else:
+            assert torch.equal(out, ref), f"variant {v} differs from variant 0 at full size"

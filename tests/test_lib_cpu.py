@@ -1,0 +1,170 @@
+"""Host-side checks of the C-ABI library that need no GPU: every declared
+symbol is exported, the host-CPU Jacobi variants are bit-exact against the
+oracle, and the runtime's state machine (RoundRobin, train trigger,
+persistence, argument errors) follows the oracle's explorer."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "adaptomp.h")
+
+
+@pytest.fixture(scope="module")
+def ao():
+    import paper_2303_08873_amd as ao
+    return ao
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_symbols_exported(ao):
+    names = _declared_functions()
+    assert "region_declare_variants" in names and "selector_train" in names
+    for n in names:
+        assert hasattr(ao.lib, n), f"{n} declared in adaptomp.h but not exported"
+
+
+def _host_region(ao, name, model_type="roundrobin", min_train=0):
+    vs = ao.jacobi_variants_sweep()[5:]
+    return ao.region_declare_variants(name, ao.AO_JACOBI7_F64, vs, min_train, model_type)
+
+
+@pytest.mark.parametrize("shape,S", [((20, 17, 9), 3), ((1, 1, 40), 2), ((65, 3, 7), 1),
+                                     ((5, 130, 2), 4), ((2, 2, 2), 0)])
+def test_host_variants_bit_exact(ao, orc, shape, S):
+    nx, ny, nz = shape
+    u0 = synth.grid_u01(nx, ny, nz, seed=7)
+    want = orc.jacobi7(u0, nx, ny, nz, S)
+    h = _host_region(ao, f"host_exact_{nx}_{ny}_{nz}_{S}")
+    out = np.zeros_like(u0)
+    a = ao.jacobi_args(u0, out, nx, ny, nz, S, resident=0)
+    for v in range(5):
+        out[:] = -1.0
+        ao.region_run(h, a, variant=v)
+        assert np.array_equal(out, want), v
+    ao.region_destroy(h)
+
+
+def test_roundrobin_and_trigger_follow_oracle(ao, orc):
+    # mlp model type: the trigger attempts training when the oracle explorer
+    # says so; with no GPU here the training fails, which region_stats counts.
+    h = _host_region(ao, "rr_trigger", model_type="mlp", min_train=7)
+    ex = orc.RoundRobinExplorer(5, min_train=7)
+    u0 = synth.grid_u01(6, 5, 4, seed=3)
+    out = np.zeros_like(u0)
+    a = ao.jacobi_args(u0, out, 6, 5, 4, 1, resident=0)
+    feats = [[1.0, 0, 0, 0, 0, 0], [1.0, 0, 0, 0, 0, 0], [2.0, 0, 0, 0, 0, 0]]
+    fired_at = None
+    for k in range(9):
+        f = feats[min(k // 3, 2)] if k < 6 else [float(k), 0, 0, 0, 0, 0]
+        rc, v = ao.region_run(h, a, features=f)
+        want_v, fire = ex.step(f)
+        assert v == want_v and rc == ao.AO_NOTE_UNTRAINED
+        st = ao.region_stats(h)
+        if fire:
+            fired_at = k
+        assert st.unique == len(ex.unique)
+        if ao.ao_device_cus() == 0:
+            assert st.train_failures == (1 if fired_at is not None else 0)
+            if fired_at is not None:
+                ex.trained = False  # the library keeps exploring after a failed training
+        elif fire:
+            assert st.trained == 1 and st.trainings == 1
+            break
+    assert fired_at is not None
+    ao.region_destroy(h)
+
+
+def test_declare_idempotent_and_conflict(ao):
+    vs = ao.jacobi_variants_sweep()[5:]
+    h1 = ao.region_declare_variants("idem", ao.AO_JACOBI7_F64, vs)
+    h2 = ao.region_declare_variants("idem", ao.AO_JACOBI7_F64, vs)
+    assert h1.value == h2.value
+    with pytest.raises(ao.AdaptError) as e:
+        ao.region_declare_variants("idem", ao.AO_JACOBI7_F64, vs[:3])
+    assert e.value.code == -5
+    ao.region_destroy(h1)
+
+
+def test_argument_errors(ao):
+    h = _host_region(ao, "argerr")
+    u0 = np.zeros(8)
+    out = np.zeros(8)
+    with pytest.raises(ao.AdaptError) as e:
+        ao.region_run(h, ao.jacobi_args(u0, u0, 2, 2, 2, 1, resident=0), variant=0)
+    assert e.value.code == -1  # u0 and out overlap
+    with pytest.raises(ao.AdaptError):
+        ao.region_run(h, ao.jacobi_args(u0, out, 2, 2, 2, 1, resident=0), variant=5)
+    with pytest.raises(ao.AdaptError):
+        ao.region_run(h, ao.jacobi_args(u0, out, -1, 2, 2, 1, resident=0), variant=0)
+    bad = ao.Variant(ao.AO_TARGET_HOST, ao.FAM_JACOBI_DIRECT, 64, 1, 1, 0)
+    with pytest.raises(ao.AdaptError):
+        ao.region_declare_variants("badvar", ao.AO_JACOBI7_F64, [bad])
+    with pytest.raises(ao.AdaptError):
+        ao.region_declare_variants("badtype", ao.AO_JACOBI7_F64, [ao.jacobi_variants_sweep()[5]],
+                                   model_type="forest")
+    with pytest.raises(ao.AdaptError):
+        ao.region_declare_variants("toomany", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep() * 2)
+    ao.region_destroy(h)
+
+
+def test_save_load_roundtrip_and_corruption(ao, tmp_path):
+    h = _host_region(ao, "persist")
+    u0 = synth.grid_u01(5, 4, 3, seed=2)
+    out = np.zeros_like(u0)
+    a = ao.jacobi_args(u0, out, 5, 4, 3, 2, resident=0)
+    for _ in range(7):
+        ao.region_run(h, a)
+    ao.region_record(h, [3.0, 1, 1, 1, 1, 0], 2, 0.5)
+    f0, v0, s0 = ao.region_records(h)
+    path = str(tmp_path / "db.bin")
+    ao.region_save(h, path)
+    h2 = _host_region(ao, "persist2")
+    ao.region_load(h2, path)
+    f1, v1, s1 = ao.region_records(h2)
+    assert f0 == f1 and v0 == v1 and s0 == s1 and len(v0) == 8
+    assert ao.region_stats(h2).unique == ao.region_stats(h).unique
+    raw = bytearray(open(path, "rb").read())
+    raw[40] ^= 0xFF
+    bad = str(tmp_path / "bad.bin")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(ao.AdaptError) as e:
+        ao.region_load(h2, bad)
+    assert e.value.code == -6
+    assert ao.region_records(h2)[1] == v0  # unchanged after a failed load
+    with pytest.raises(ao.AdaptError):
+        ao.region_load(h2, str(tmp_path / "missing.bin"))
+    other = ao.region_declare_variants("persist_other", ao.AO_JACOBI7_F64,
+                                       ao.jacobi_variants_sweep()[5:8])
+    with pytest.raises(ao.AdaptError):
+        ao.region_load(other, path)
+    for x in (h, h2, other):
+        ao.region_destroy(x)
+
+
+def test_record_validation(ao):
+    h = _host_region(ao, "recval")
+    with pytest.raises(ao.AdaptError):
+        ao.region_record(h, [1, 2, 3, 4, 5, 6], 9, 1.0)
+    with pytest.raises(ao.AdaptError):
+        ao.region_record(h, [1, 2, 3, 4, 5, 6], 1, -1.0)
+    ao.region_record(h, [1, 2, 3, 4, 5, 6], 1, 1e-3)
+    assert ao.region_stats(h).records == 1
+    ao.region_destroy(h)
+
+
+def test_selector_select_untrained_returns_exploration_id(ao):
+    h = _host_region(ao, "seluntrained")
+    rc, ids = ao.selector_select(h, [[1, 2, 3, 4, 5, 6]] * 3)
+    assert rc == ao.AO_NOTE_UNTRAINED and ids == [0, 0, 0]
+    ao.region_destroy(h)
