@@ -76,6 +76,8 @@ enum ao_family {
     AO_FAM_JACOBI_DIRECT = 0, /* GPU: one thread per point, block bx*by */
     AO_FAM_JACOBI_ZMARCH = 1, /* GPU: bx*by LDS plane tile + halo, marches bz planes */
     AO_FAM_JACOBI_HOST = 2,   /* host CPU (OpenMP): tiles bx (0 = whole row) by by rows */
+    AO_FAM_JACOBI_ZREG = 3,   /* GPU: register z-march, strip bx (64|128) wide, by (1|2|4|8)
+                                 rows per wave, 4 waves per block, bz planes per block */
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
     AO_FAM_SPMV_MERGE_PATH = 12  /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
@@ -286,6 +288,12 @@ int region_clear_memo(ao_region* r);
 int region_destroy(ao_region* r);
 
 const char* ao_last_error(void);
+
+/* Plain FP64 stream copy dst[0..n) = src[0..n) on device memory (16-byte
+ * aligned), enqueued on stream: the achievable-bandwidth probe that region
+ * bandwidth is compared with, and the calibration kernel of the byte
+ * counters.  nontemporal != 0 uses streaming stores. */
+int ao_hbm_copy(const double* src, double* dst, int64_t n, int nontemporal, void* stream);
 
 /* Number of compute units of the current device (0 if none). */
 int ao_device_cus(void);

@@ -12,7 +12,7 @@ AO_OK, AO_NOTE_UNTRAINED, AO_NOTE_FALLBACK = 0, 1, 2
 AO_MAX_VARIANTS, AO_MAX_FEATURES, AO_MLP_PARAMS = 12, 6, 5388
 AO_JACOBI7_F64, AO_CSR_SPMV_F64 = 0, 1
 AO_TARGET_GPU, AO_TARGET_HOST = 0, 1
-FAM_JACOBI_DIRECT, FAM_JACOBI_ZMARCH, FAM_JACOBI_HOST = 0, 1, 2
+FAM_JACOBI_DIRECT, FAM_JACOBI_ZMARCH, FAM_JACOBI_HOST, FAM_JACOBI_ZREG = 0, 1, 2, 3
 FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH = 10, 11, 12
 AO_VF_NT_STORE = 1
 AO_PROFILE_RECORD = 1
@@ -89,6 +89,7 @@ def _load():
         "region_clear_memo": [P],
         "region_destroy": [P],
         "ao_device_cus": [],
+        "ao_hbm_copy": [P, P, ctypes.c_int64, I, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -222,6 +223,10 @@ def region_clear_memo(region) -> None:
 
 def region_destroy(region) -> None:
     _check(lib.region_destroy(region))
+
+
+def ao_hbm_copy(src, dst, n: int, nontemporal: bool = False, stream=None) -> None:
+    _check(lib.ao_hbm_copy(_ptr(src), _ptr(dst), n, 1 if nontemporal else 0, _stream(stream)))
 
 
 def ao_device_cus() -> int:

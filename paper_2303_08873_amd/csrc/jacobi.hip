@@ -16,7 +16,15 @@
 //          a one-point halo, so each interior point is read from global
 //          memory once per sweep.
 //
-// Both map blockIdx.x to tiles XCD-aware: the hardware deals workgroups to
+//  zreg    no LDS and no barriers: each wave owns a (64*VX)-wide x strip of
+//          R rows and marches bz planes.  Plane k-1, k and k+1 of its R rows
+//          live in registers (the plane k+1 rows are the loads issued in
+//          iteration k), the x-neighbours come from the adjacent lanes by
+//          cross-lane moves (the two strip edges are loaded by lanes 0 and
+//          63), the y-neighbours from the wave's own rows plus two halo rows.
+//          A block is 4 such waves stacked in y (tile 64*VX x 4R).
+//
+// All map blockIdx.x to tiles XCD-aware: the hardware deals workgroups to
 // the 8 XCDs round-robin, so consecutive logical tiles (which share z- and
 // y-neighbour planes) are remapped to the same XCD and meet in its L2.
 #include "internal.h"
@@ -115,6 +123,149 @@ __global__ __launch_bounds__(1024) void jac_zmarch(const double* __restrict__ sr
     }
 }
 
+constexpr int kZregWaves = 4;
+
+template <int VX>
+struct Vec;
+template <>
+struct Vec<1> {
+    double v[1];
+};
+template <>
+struct Vec<2> {
+    double v[2];
+};
+
+// Load VX consecutive points of one row starting at x = i (zero outside the
+// grid or when `ok` is false).
+template <int VX>
+__device__ __forceinline__ Vec<VX> load_row(const double* __restrict__ row, int i, int nx,
+                                            bool ok) {
+    Vec<VX> r;
+    if constexpr (VX == 2) {
+        if (ok && i + 1 < nx) {
+            const double2 t = *reinterpret_cast<const double2*>(row + i);
+            r.v[0] = t.x;
+            r.v[1] = t.y;
+        } else {
+            r.v[0] = (ok && i < nx) ? row[i] : 0.0;
+            r.v[1] = 0.0;
+        }
+    } else {
+        r.v[0] = (ok && i < nx) ? row[i] : 0.0;
+    }
+    return r;
+}
+
+template <int R, int VX, bool NT>
+__global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __restrict__ src,
+                                                             double* __restrict__ dst, int nx,
+                                                             int ny, int nz, int nbx, int nby,
+                                                             int bz, unsigned nblocks) {
+    constexpr int TW = 64 * VX;
+    const unsigned b = xcd_remap(blockIdx.x, nblocks);
+    const int bi = (int)(b % (unsigned)nbx);
+    const unsigned t = b / (unsigned)nbx;
+    const int bj = (int)(t % (unsigned)nby);
+    const int kb = (int)(t / (unsigned)nby);
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int i0 = bi * TW;
+    const int i = i0 + lane * VX;
+    const int j0 = (bj * kZregWaves + wave) * R;
+    if (j0 >= ny) return;  // whole wave outside the grid (uniform)
+    const int k0 = kb * bz;
+    const int k1 = min(nz, k0 + bz);
+    const size_t plane = (size_t)nx * (size_t)ny;
+    // edge lanes fetch the neighbour just outside the strip
+    const int ie = (lane == 0) ? i0 - 1 : i0 + TW;
+    const bool edge = (lane == 0 && i0 > 0) || (lane == 63 && i0 + TW < nx);
+
+    Vec<VX> below[R], cur[R], above[R];
+    double ex[R];
+    auto row_ptr = [&](int k, int j) { return src + (size_t)k * plane + (size_t)j * nx; };
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool okj = j0 + r < ny;
+        below[r] = load_row<VX>(k0 > 0 ? row_ptr(k0 - 1, min(j0 + r, ny - 1)) : src, i, nx,
+                                okj && k0 > 0);
+        cur[r] = load_row<VX>(row_ptr(k0, min(j0 + r, ny - 1)), i, nx, okj);
+    }
+    for (int k = k0; k < k1; ++k) {
+        const bool has_up = k + 1 < nz;
+        const Vec<VX> ym_row = load_row<VX>(row_ptr(k, max(j0 - 1, 0)), i, nx, j0 > 0);
+        const Vec<VX> yp_row = load_row<VX>(row_ptr(k, min(j0 + R, ny - 1)), i, nx, j0 + R < ny);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool okj = j0 + r < ny;
+            const double* rp = row_ptr(k, min(j0 + r, ny - 1));
+            ex[r] = (edge && okj) ? rp[ie] : 0.0;
+            above[r] = load_row<VX>(has_up ? row_ptr(k + 1, min(j0 + r, ny - 1)) : src, i, nx,
+                                    okj && has_up);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = j0 + r;
+            // x neighbours: within the lane, then across lanes
+            const double left = __shfl_up(cur[r].v[VX - 1], 1);
+            const double right = __shfl_down(cur[r].v[0], 1);
+            const double xl = (lane == 0) ? ex[r] : left;
+            const double xr = (lane == 63) ? ex[r] : right;
+#pragma unroll
+            for (int q = 0; q < VX; ++q) {
+                const double xm = (q == 0) ? xl : cur[r].v[q - 1];
+                const double xp = (q == VX - 1) ? xr : cur[r].v[q + 1];
+                const double ym = (r == 0) ? ym_row.v[q] : cur[r - 1].v[q];
+                const double yp = (r == R - 1) ? yp_row.v[q] : cur[r + 1].v[q];
+                double v = xm + xp;
+                v = v + ym;
+                v = v + yp;
+                v = v + below[r].v[q];
+                v = v + above[r].v[q];
+                if (j < ny && i + q < nx)
+                    store<NT>(dst + (size_t)k * plane + (size_t)j * nx + (i + q), v * kC);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            below[r] = cur[r];
+            cur[r] = above[r];
+        }
+    }
+}
+
+template <int R, int VX>
+hipError_t launch_zreg(bool nt, dim3 grid, hipStream_t s, const double* src, double* dst, int nx,
+                       int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
+    if (nt)
+        hipLaunchKernelGGL((jac_zreg<R, VX, true>), grid, dim3(64 * kZregWaves), 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
+    else
+        hipLaunchKernelGGL((jac_zreg<R, VX, false>), grid, dim3(64 * kZregWaves), 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src,
+                                              double* __restrict__ dst, int64_t n, int nt) {
+    const int64_t base = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (base + 3 < n) {
+        const double2 a = *reinterpret_cast<const double2*>(src + base);
+        const double2 c = *reinterpret_cast<const double2*>(src + base + 2);
+        if (nt) {
+            __builtin_nontemporal_store(a.x, dst + base);
+            __builtin_nontemporal_store(a.y, dst + base + 1);
+            __builtin_nontemporal_store(c.x, dst + base + 2);
+            __builtin_nontemporal_store(c.y, dst + base + 3);
+        } else {
+            *reinterpret_cast<double2*>(dst + base) = a;
+            *reinterpret_cast<double2*>(dst + base + 2) = c;
+        }
+    } else {
+        for (int64_t q = base; q < n; ++q) dst[q] = src[q];
+    }
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace
@@ -123,7 +274,8 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
                             int nz, hipStream_t s) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
     const int bx = v.bx, by = v.by;
-    if (bx <= 0 || by <= 0 || (int64_t)bx * by > 1024 || (bx * by) % 64 != 0)
+    if (bx <= 0 || by <= 0) return hipErrorInvalidConfiguration;
+    if (v.family != AO_FAM_JACOBI_ZREG && ((int64_t)bx * by > 1024 || (bx * by) % 64 != 0))
         return hipErrorInvalidConfiguration;
     const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
     const int nbx = cdiv(nx, bx), nby = cdiv(ny, by);
@@ -155,7 +307,35 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
                                nby, bz, (unsigned)nb);
         return hipGetLastError();
     }
+    if (v.family == AO_FAM_JACOBI_ZREG) {
+        // bx = strip width (64 or 128 points), by = rows per wave, bz = planes
+        const int VX = bx / 64, R = by, bz = v.bz;
+        if ((bx != 64 && bx != 128) || bz <= 0) return hipErrorInvalidConfiguration;
+        if (VX == 2 && ((nx & 1) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)))
+            return hipErrorInvalidConfiguration;
+        const int nbxz = cdiv(nx, bx), nbyz = cdiv(ny, kZregWaves * R);
+        const int64_t nb = (int64_t)nbxz * nbyz * cdiv(nz, bz);
+        if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
+        const dim3 grid((unsigned)nb);
+        const unsigned u = (unsigned)nb;
+#define AO_ZREG(RR, VV)                                                                  \
+    if (R == RR && VX == VV)                                                             \
+        return launch_zreg<RR, VV>(nt, grid, s, src, dst, nx, ny, nz, nbxz, nbyz, bz, u);
+        AO_ZREG(1, 1) AO_ZREG(2, 1) AO_ZREG(4, 1) AO_ZREG(8, 1)
+        AO_ZREG(1, 2) AO_ZREG(2, 2) AO_ZREG(4, 2) AO_ZREG(8, 2)
+#undef AO_ZREG
+        return hipErrorInvalidConfiguration;
+    }
     return hipErrorInvalidValue;
+}
+
+hipError_t hbm_copy(const double* src, double* dst, int64_t n, bool nt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return hipErrorInvalidValue;
+    const int64_t blocks = (n + 1023) / 1024;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, nt ? 1 : 0);
+    return hipGetLastError();
 }
 
 }  // namespace ao

@@ -168,8 +168,13 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             return AO_OK;
         }
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "unknown target");
-        if (v.family != AO_FAM_JACOBI_DIRECT && v.family != AO_FAM_JACOBI_ZMARCH)
+        if (v.family != AO_FAM_JACOBI_DIRECT && v.family != AO_FAM_JACOBI_ZMARCH &&
+            v.family != AO_FAM_JACOBI_ZREG)
             return fail(AO_EINVAL, at + "unknown GPU Jacobi family");
+        if (v.family == AO_FAM_JACOBI_ZREG &&
+            ((v.bx != 64 && v.bx != 128) || (v.by != 1 && v.by != 2 && v.by != 4 && v.by != 8) ||
+             v.bz <= 0))
+            return fail(AO_EINVAL, at + "register z-march needs bx 64|128, by 1|2|4|8, bz > 0");
         if (v.bx <= 0 || v.by <= 0) return fail(AO_EINVAL, at + "block sizes must be positive");
         if (v.family == AO_FAM_JACOBI_ZMARCH && v.bz <= 0)
             return fail(AO_EINVAL, at + "z-march needs bz > 0");
@@ -866,6 +871,17 @@ const char kMagic[8] = {'A', 'O', 'M', 'P', 'D', 'B', 0, 1};
 extern "C" {
 
 const char* ao_last_error(void) { return g_err.c_str(); }
+
+int ao_hbm_copy(const double* src, double* dst, int64_t n, int nontemporal, void* stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) return fail(AO_EINVAL, "bad arguments");
+    hipError_t e = hbm_copy(src, dst, n, nontemporal != 0, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorInvalidValue ? AO_EINVAL : AO_EHIP,
+                    hip_msg("copy (buffers must be 16-byte aligned)", e));
+    }
+    return AO_OK;
+}
 
 int ao_device_cus(void) {
     int dev = 0;

@@ -97,7 +97,12 @@ def test_nontemporal_and_zmarch_shapes(env, orc):
           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 64, 4, 7, ao.AO_VF_NT_STORE),
           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 128, 8, 1, 0),
           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZMARCH, 16, 4, 100, 0),
-          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 256, 4, 1, 0)]
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 256, 4, 1, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, 64, 1, 5, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, 64, 8, 64, ao.AO_VF_NT_STORE),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, 128, 2, 16, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, 128, 4, 3, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, 128, 8, 100, 0)]
     h = ao.region_declare_variants("gpu_shapes", ao.AO_JACOBI7_F64, vs, model_type="roundrobin")
     a = ao.jacobi_args(u0, out, nx, ny, nz, S)
     for v in range(len(vs)):
@@ -105,6 +110,47 @@ def test_nontemporal_and_zmarch_shapes(env, orc):
         ao.region_run(h, a, stream=st, variant=v)
         torch.cuda.synchronize()
         _check(out.cpu().numpy(), want)
+
+
+ZREG = [(64, 1, 1), (64, 2, 7), (64, 4, 64), (64, 8, 3), (128, 1, 2), (128, 2, 9), (128, 4, 5),
+        (128, 8, 64)]
+
+
+@pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 2),
+                                     ((257, 3, 4), 1), ((64, 32, 16), 2), ((6, 6, 6), 5)])
+def test_zreg_all_shapes(env, orc, shape, S):
+    # register z-march: every strip width / rows-per-wave / plane count,
+    # ragged in every direction (odd nx refuses the 128-wide strip, which
+    # loads pairs, and masks it)
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=31 + nx)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, bx, by, bz, 0) for bx, by, bz in ZREG]
+    h = ao.region_declare_variants(f"gpu_zreg_{nx}_{ny}_{nz}", ao.AO_JACOBI7_F64, vs,
+                                   model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+    for v, (bx, by, bz) in enumerate(ZREG):
+        out.fill_(-1.0)
+        if bx == 128 and nx % 2:
+            with pytest.raises(ao.AdaptError):
+                ao.region_run(h, a, stream=st, variant=v)
+            continue
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        _check(out.cpu().numpy(), want)
+
+
+def test_hbm_copy_probe(env):
+    ao, torch, dev, st = env
+    for n in (0, 1, 5, 4096, 1000003):
+        src = torch.arange(n, dtype=torch.float64, device=dev)
+        dst = torch.full((n,), -1.0, dtype=torch.float64, device=dev)
+        ao.ao_hbm_copy(src, dst, n, nontemporal=(n % 2 == 1), stream=st)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
 
 
 def test_edge_cases(env, orc):
