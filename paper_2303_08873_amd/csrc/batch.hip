@@ -1,17 +1,442 @@
-// Batched execution of many uneven Jacobi instances (placeholder until the
-// persistent kernel lands).
+// Batched execution of many uneven Jacobi instances in one launch per sweep.
+//
+// Every (instance, tile) pair is a work item; a persistent kernel -- grid
+// sized to the machine, each workgroup striding over the item list --
+// performs one sweep of every instance, and the S sweeps are captured once
+// in a HIP graph so a single graph launch runs the whole batch.  Instances
+// are bucketed by their largest dimension and each bucket uses one tile
+// shape, picked by the autotuner (batch_autotune) from a fixed candidate
+// table by timing the bucket alone.  The per-point arithmetic is the
+// region's ((((xm+xp)+ym)+yp)+zm)+zp) * fl(1/6), so each instance's result
+// is bit-identical to a standalone run.
+//
+// Tile kinds:
+//  direct  tx*ty*tz points, threads stride over them, six neighbour loads
+//          each (small grids, where a 64-wide strip would idle lanes);
+//  zreg    the register z-march: each of the 4 waves owns a 64-wide strip of
+//          R rows and marches tz planes, x-neighbours by cross-lane moves.
+#include <math.h>
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
 #include "internal.h"
+
+namespace ao {
+namespace {
+
+constexpr double kC = 0x1.5555555555555p-3;  // fl(1/6)
+constexpr int kThreads = 256;
+constexpr int kBuckets = 5;
+
+enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2 };
+struct TileCfg {
+    int kind, tx, ty, tz;
+};
+// candidate tiles (index = candidate id)
+constexpr TileCfg kCands[] = {
+    {kDirect, 8, 8, 4},  {kDirect, 16, 16, 1}, {kDirect, 16, 8, 2},  {kDirect, 32, 8, 1},
+    {kDirect, 64, 4, 1}, {kDirect, 16, 16, 4}, {kDirect, 8, 8, 16},  {kZreg1, 64, 4, 16},
+    {kZreg2, 64, 8, 32}, {kZreg2, 64, 8, 64},  {kZreg1, 64, 4, 64},  {kZreg2, 64, 8, 16},
+};
+constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
+// default candidate per bucket before autotuning
+constexpr int kDefaultCand[kBuckets] = {0, 1, 3, 8, 8};
+__constant__ TileCfg c_cands[kNumCands];
+
+struct Item {
+    int32_t inst, x0, y0, z0, cand;
+};
+struct Inst {
+    const double* u0;
+    double* out;
+    double* tmp;
+    int32_t nx, ny, nz, sweeps;
+};
+
+__device__ __forceinline__ const double* src_of(const Inst& in, int s) {
+    return s == 0 ? in.u0 : (((in.sweeps - s) % 2 == 0) ? in.out : in.tmp);
+}
+__device__ __forceinline__ double* dst_of(const Inst& in, int s) {
+    return ((in.sweeps - 1 - s) % 2 == 0) ? in.out : in.tmp;
+}
+
+__device__ void tile_direct(const Inst& in, const double* __restrict__ src, double* __restrict__ dst,
+                            const Item& it, const TileCfg& c) {
+    const int nx = in.nx, ny = in.ny, nz = in.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int npts = c.tx * c.ty * c.tz;
+    for (int p = (int)threadIdx.x; p < npts; p += kThreads) {
+        const int i = it.x0 + p % c.tx;
+        const int j = it.y0 + (p / c.tx) % c.ty;
+        const int k = it.z0 + p / (c.tx * c.ty);
+        if (i >= nx || j >= ny || k >= nz) continue;
+        const size_t idx = (size_t)k * plane + (size_t)j * nx + i;
+        const double xm = i > 0 ? src[idx - 1] : 0.0;
+        const double xp = i + 1 < nx ? src[idx + 1] : 0.0;
+        const double ym = j > 0 ? src[idx - nx] : 0.0;
+        const double yp = j + 1 < ny ? src[idx + nx] : 0.0;
+        const double zm = k > 0 ? src[idx - plane] : 0.0;
+        const double zp = k + 1 < nz ? src[idx + plane] : 0.0;
+        double v = xm + xp;
+        v = v + ym;
+        v = v + yp;
+        v = v + zm;
+        v = v + zp;
+        dst[idx] = v * kC;
+    }
+}
+
+template <int R>
+__device__ void tile_zreg(const Inst& in, const double* __restrict__ src, double* __restrict__ dst,
+                          const Item& it, const TileCfg& c) {
+    const int nx = in.nx, ny = in.ny, nz = in.nz;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int i0 = it.x0, i = i0 + lane;
+    const int j0 = it.y0 + wave * R;
+    if (j0 >= ny) return;  // wave-uniform
+    const int k0 = it.z0, k1 = min(nz, k0 + c.tz);
+    const size_t plane = (size_t)nx * ny;
+    const bool xin = i < nx;
+    const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
+    const bool edge = (lane == 0 && i0 > 0) || (lane == 63 && i0 + 64 < nx);
+    auto at = [&](int k, int j, int x, bool ok) -> double {
+        return ok ? src[(size_t)k * plane + (size_t)j * nx + x] : 0.0;
+    };
+    double below[R], cur[R], above[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool okj = j0 + r < ny;
+        below[r] = at(k0 - 1, j0 + r, i, okj && xin && k0 > 0);
+        cur[r] = at(k0, j0 + r, i, okj && xin);
+    }
+    for (int k = k0; k < k1; ++k) {
+        const double ymv = at(k, j0 - 1, i, j0 > 0 && xin);
+        const double ypv = at(k, j0 + R, i, j0 + R < ny && xin);
+        double ex[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool okj = j0 + r < ny;
+            ex[r] = at(k, j0 + r, ie, edge && okj);
+            above[r] = at(k + 1, j0 + r, i, okj && xin && k + 1 < nz);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double left = __shfl_up(cur[r], 1);
+            const double right = __shfl_down(cur[r], 1);
+            const double xm = (lane == 0) ? ex[r] : left;
+            const double xp = (lane == 63) ? ex[r] : right;
+            const double ym = (r == 0) ? ymv : cur[r - 1];
+            const double yp = (r == R - 1) ? ypv : cur[r + 1];
+            double v = xm + xp;
+            v = v + ym;
+            v = v + yp;
+            v = v + below[r];
+            v = v + above[r];
+            if (xin && j0 + r < ny) dst[(size_t)k * plane + (size_t)(j0 + r) * nx + i] = v * kC;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            below[r] = cur[r];
+            cur[r] = above[r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_sweep(const Inst* __restrict__ insts,
+                                                          const Item* __restrict__ items,
+                                                          int nitems, int sweep) {
+    for (int w = (int)blockIdx.x; w < nitems; w += (int)gridDim.x) {
+        const Item it = items[w];
+        const Inst in = insts[it.inst];
+        if (sweep >= in.sweeps) continue;
+        const TileCfg c = c_cands[it.cand];
+        const double* src = src_of(in, sweep);
+        double* dst = dst_of(in, sweep);
+        if (c.kind == kDirect)
+            tile_direct(in, src, dst, it, c);
+        else if (c.kind == kZreg1)
+            tile_zreg<1>(in, src, dst, it, c);
+        else
+            tile_zreg<2>(in, src, dst, it, c);
+    }
+}
+
+int bucket_of(int nx, int ny, int nz) {
+    const int m = std::max(nx, std::max(ny, nz));
+    if (m <= 16) return 0;
+    if (m <= 32) return 1;
+    if (m <= 64) return 2;
+    if (m <= 128) return 3;
+    return 4;
+}
+
+int64_t item_cost(const Inst& in, const TileCfg& c) {
+    (void)in;
+    return (int64_t)c.tx * c.ty * c.tz;
+}
+
+}  // namespace
+}  // namespace ao
 
 using namespace ao;
 
 struct ao_batch {
-    int dummy;
+    std::vector<Inst> insts;
+    std::vector<int> bucket;
+    int cand[kBuckets];
+    int max_sweeps = 0;
+    Inst* d_insts = nullptr;
+    Item* d_items = nullptr;
+    int nitems = 0;
+    int items_per_bucket[kBuckets] = {0};
+    double* scratch = nullptr;
+    int grid = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_dirty = true;
+    ~ao_batch() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (cap_stream) hipStreamDestroy(cap_stream);
+        if (d_items) hipFree(d_items);
+        if (d_insts) hipFree(d_insts);
+        if (scratch) hipFree(scratch);
+    }
 };
 
-extern "C" {
-int batch_create(const ao_args*, int, ao_batch**) { return fail(AO_ESTATE, "batched execution not available"); }
-int batch_autotune(ao_batch*, void*, int, int, int*) { return fail(AO_ESTATE, "batched execution not available"); }
-int batch_run(ao_batch*, void*, int) { return fail(AO_ESTATE, "batched execution not available"); }
-int batch_info(const ao_batch*, int*, int*, int*) { return fail(AO_ESTATE, "batched execution not available"); }
-int batch_destroy(ao_batch*) { return fail(AO_ESTATE, "batched execution not available"); }
+namespace ao {
+namespace {
+
+std::vector<Item> make_items(const ao_batch* b, int only_bucket, int cand_override) {
+    std::vector<std::pair<int64_t, Item>> v;
+    for (size_t q = 0; q < b->insts.size(); ++q) {
+        const int bk = b->bucket[q];
+        if (only_bucket >= 0 && bk != only_bucket) continue;
+        const int cand = cand_override >= 0 ? cand_override : b->cand[bk];
+        const TileCfg& c = kCands[cand];
+        const Inst& in = b->insts[q];
+        if ((int64_t)in.nx * in.ny * in.nz == 0 || in.sweeps == 0) continue;
+        for (int z = 0; z < in.nz; z += c.tz)
+            for (int y = 0; y < in.ny; y += c.ty)
+                for (int x = 0; x < in.nx; x += c.tx)
+                    v.push_back({item_cost(in, c), Item{(int32_t)q, x, y, z, cand}});
+    }
+    // larger items first: the strided loop then ends with the small ones
+    std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+    std::vector<Item> out;
+    out.reserve(v.size());
+    for (auto& p : v) out.push_back(p.second);
+    return out;
 }
+
+hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
+    if (b->d_items) hipFree(b->d_items);
+    b->d_items = nullptr;
+    b->nitems = (int)items.size();
+    if (items.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(&b->d_items, items.size() * sizeof(Item));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t launch_sweeps(ao_batch* b, hipStream_t s) {
+    for (const Inst& in : b->insts) {  // zero sweeps: the result is the input
+        const size_t n = (size_t)in.nx * in.ny * in.nz;
+        if (in.sweeps == 0 && n > 0) {
+            hipError_t e = hipMemcpyAsync(in.out, in.u0, n * 8, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (b->nitems == 0) return hipSuccess;
+    const int grid = std::min(b->nitems, b->grid);
+    for (int sw = 0; sw < b->max_sweeps; ++sw) {
+        hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kThreads), 0, s, b->d_insts, b->d_items,
+                           b->nitems, sw);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int rebuild(ao_batch* b) {
+    hipError_t e = upload_items(b, make_items(b, -1, -1));
+    if (e != hipSuccess) return fail(AO_EHIP, std::string("batch items: ") + hipGetErrorString(e));
+    for (int k = 0; k < kBuckets; ++k) b->items_per_bucket[k] = 0;
+    for (size_t q = 0; q < b->insts.size(); ++q) {
+        const TileCfg& c = kCands[b->cand[b->bucket[q]]];
+        const Inst& in = b->insts[q];
+        if ((int64_t)in.nx * in.ny * in.nz == 0 || in.sweeps == 0) continue;
+        b->items_per_bucket[b->bucket[q]] += ((in.nx + c.tx - 1) / c.tx) *
+                                             ((in.ny + c.ty - 1) / c.ty) *
+                                             ((in.nz + c.tz - 1) / c.tz);
+    }
+    b->graph_dirty = true;
+    return AO_OK;
+}
+
+}  // namespace
+}  // namespace ao
+
+extern "C" {
+
+int batch_create(const ao_args* inst, int count, ao_batch** out) {
+    if (!out || count < 1 || !inst) return fail(AO_EINVAL, "need count >= 1 instances and out");
+    std::unique_ptr<ao_batch> b(new (std::nothrow) ao_batch());
+    if (!b) return fail(AO_ENOMEM, "batch allocation");
+    size_t total = 0;
+    for (int q = 0; q < count; ++q) {
+        const ao_args& a = inst[q];
+        if (a.kind != AO_JACOBI7_F64 || a.resident != 1)
+            return fail(AO_EINVAL, "batched instances must be device-resident Jacobi regions");
+        if (a.nx < 0 || a.ny < 0 || a.nz < 0 || a.sweeps < 0)
+            return fail(AO_EINVAL, "negative size or sweep count");
+        const size_t n = (size_t)a.nx * a.ny * a.nz;
+        if (n > 0 && (!a.u0 || !a.out)) return fail(AO_EINVAL, "u0/out is NULL");
+        if (n > 0) {
+            const char* u = (const char*)a.u0;
+            const char* o = (const char*)a.out;
+            if (u < o + n * 8 && o < u + n * 8) return fail(AO_EINVAL, "u0 and out overlap");
+        }
+        total += n;
+    }
+    hipError_t e = hipMalloc(&b->scratch, std::max<size_t>(total, 1) * sizeof(double));
+    if (e != hipSuccess) return fail(AO_ENOMEM, std::string("batch scratch: ") + hipGetErrorString(e));
+    size_t off = 0;
+    for (int q = 0; q < count; ++q) {
+        const ao_args& a = inst[q];
+        Inst in{a.u0, a.out, b->scratch + off, a.nx, a.ny, a.nz, a.sweeps};
+        off += (size_t)a.nx * a.ny * a.nz;
+        b->insts.push_back(in);
+        b->bucket.push_back(bucket_of(a.nx, a.ny, a.nz));
+        b->max_sweeps = std::max(b->max_sweeps, a.sweeps);
+    }
+    for (int k = 0; k < kBuckets; ++k) b->cand[k] = kDefaultCand[k];
+    e = hipMalloc(&b->d_insts, b->insts.size() * sizeof(Inst));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_insts, b->insts.data(), b->insts.size() * sizeof(Inst),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_cands), kCands, sizeof(kCands));
+    if (e != hipSuccess) return fail(AO_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->grid = std::max(1, cus) * 8;
+    int rc = rebuild(b.get());
+    if (rc) return rc;
+    *out = b.release();
+    return AO_OK;
+}
+
+int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen) {
+    if (!b || warmup < 0 || reps < 1) return fail(AO_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return fail(AO_EHIP, "event creation");
+    int result[kBuckets];
+    for (int k = 0; k < kBuckets; ++k) {
+        result[k] = -1;
+        bool any = false;
+        for (int bk : b->bucket) any = any || bk == k;
+        if (!any) continue;
+        double best = INFINITY;
+        for (int c = 0; c < kNumCands; ++c) {
+            e = upload_items(b, make_items(b, k, c));
+            std::vector<double> ts;
+            for (int r = 0; r < warmup + reps && e == hipSuccess; ++r) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = launch_sweeps(b, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (r >= warmup) ts.push_back(ms);
+            }
+            if (e != hipSuccess) break;
+            std::sort(ts.begin(), ts.end());
+            const double med = ts.size() % 2 ? ts[ts.size() / 2]
+                                             : 0.5 * (ts[ts.size() / 2 - 1] + ts[ts.size() / 2]);
+            if (med < best) {
+                best = med;
+                result[k] = c;
+            }
+        }
+        if (e != hipSuccess) break;
+        b->cand[k] = result[k];
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        rebuild(b);
+        return fail(AO_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    int rc = rebuild(b);
+    if (rc) return rc;
+    if (chosen)
+        for (int k = 0; k < kBuckets; ++k) chosen[k] = result[k];
+    return AO_OK;
+}
+
+int batch_run(ao_batch* b, void* stream, int use_graph) {
+    if (!b) return fail(AO_EINVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!use_graph) {
+        e = launch_sweeps(b, s);
+        if (e != hipSuccess) return fail(AO_EHIP, std::string("batch run: ") + hipGetErrorString(e));
+        return AO_OK;
+    }
+    if (b->graph_dirty || !b->exec) {
+        if (b->exec) hipGraphExecDestroy(b->exec);
+        if (b->graph) hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        if (!b->cap_stream) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_sweeps(b, b->cap_stream);
+            e = hipStreamEndCapture(b->cap_stream, &b->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(AO_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        b->graph_dirty = false;
+    }
+    e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return fail(AO_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return AO_OK;
+}
+
+int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz) {
+    if (!b) return fail(AO_EINVAL, "batch is NULL");
+    for (int k = 0; k < kBuckets; ++k) {
+        int cnt = 0;
+        for (int bk : b->bucket) cnt += bk == k;
+        if (instances) instances[k] = cnt;
+        if (items) items[k] = b->items_per_bucket[k];
+        if (tiles_xyz) {
+            const TileCfg& c = kCands[b->cand[k]];
+            tiles_xyz[3 * k] = c.tx;
+            tiles_xyz[3 * k + 1] = c.ty;
+            tiles_xyz[3 * k + 2] = c.tz;
+        }
+    }
+    return AO_OK;
+}
+
+int batch_destroy(ao_batch* b) {
+    if (!b) return fail(AO_EINVAL, "batch is NULL");
+    delete b;
+    return AO_OK;
+}
+
+}  // extern "C"

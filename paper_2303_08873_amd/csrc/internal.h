@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/adaptomp.h"
 
@@ -35,16 +36,21 @@ struct SpmvPlan {
     float features[AO_MAX_FEATURES] = {0};
     bool have_features = false;
     int32_t max_len = 0;  // longest row
-    // merge-path partition, per chunk size
-    int32_t mp_chunk = 0;
-    int32_t mp_blocks = 0;
-    int32_t* mp_start_row = nullptr;   // [mp_blocks + 1]
-    int32_t* mp_start_unit = nullptr;  // [mp_blocks + 1] unit index within the start row
-    int32_t* unit_ptr = nullptr;       // [n + 1] first 64-block unit of each row
-    double* unit_sums = nullptr;       // [units] sums of units of rows split across chunks
+    // merge-path: row-aligned 64-leaf units and one partition per chunk size
+    int32_t* unit_ptr = nullptr;  // [n + 1] first unit of each row
+    double* unit_sums = nullptr;  // [units] sums of units of rows split across chunks
     int64_t units = 0;
+    struct MergeSplit {
+        int D = 0;                  // cost per workgroup
+        int blocks = 0;
+        int32_t* srow = nullptr;    // [blocks + 1] start row of each workgroup (owns the allocation)
+        int32_t* sunit = nullptr;   // [blocks + 1] start unit within that row
+    };
+    std::vector<MergeSplit> mp;
     ~SpmvPlan();
 };
+// Build the merge-path partition for workgroups of B threads (synchronises).
+hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s);
 
 hipError_t spmv_features(SpmvPlan& p, hipStream_t s);
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,

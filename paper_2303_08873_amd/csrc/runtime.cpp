@@ -305,6 +305,17 @@ SpmvPlan* get_plan(ao_region* r, const ao_args* a, hipStream_t s, int* rc) {
         return nullptr;
     }
     p->have_features = true;
+    // merge-path partitions for the region's merge-path variants
+    for (const ao_variant& v : r->variants) {
+        if (v.family != AO_FAM_SPMV_MERGE_PATH || p->n <= 0) continue;
+        if (v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) continue;
+        e = spmv_prepare_merge(*p, v.bx, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *rc = fail(AO_EHIP, hip_msg("merge-path partition", e));
+            return nullptr;
+        }
+    }
     r->plans.push_back(std::move(p));
     return r->plans.back().get();
 }
@@ -644,8 +655,8 @@ ao_region::~ao_region() {
 }
 
 SpmvPlan::~SpmvPlan() {
-    if (mp_start_row) hipFree(mp_start_row);
-    if (mp_start_unit) hipFree(mp_start_unit);
+    for (auto& m : mp)
+        if (m.srow) hipFree(m.srow);
     if (unit_ptr) hipFree(unit_ptr);
     if (unit_sums) hipFree(unit_sums);
 }

@@ -241,9 +241,274 @@ hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const 
     return hipErrorInvalidValue;
 }
 
-hipError_t spmv_merge_path(const ao_variant&, SpmvPlan&, const int32_t*, const double*,
-                           const double*, double*, hipStream_t) {
-    return hipErrorNotSupported;
+// ---- merge-path ------------------------------------------------------------
+//
+// Units: row i is cut into nu_i = max(1, ceil(L_i / 64)) row-aligned units
+// of <= 64 leaves (an empty row keeps one empty unit so that y_i is
+// written).  Unit (i, j) costs its leaf count + 1; a workgroup takes the
+// units whose cumulative cost falls in [b*D, (b+1)*D), D = 4 * block size.
+// The cost before unit (i, j) is base_i + 65 j with
+// base_i = (row_ptr[i] - row_ptr[0]) + unit_ptr[i].
+
+namespace {
+
+// exclusive scan of per-row unit counts, three passes (1024 rows per block)
+__global__ __launch_bounds__(1024) void k_units_block(int n, const int32_t* __restrict__ row_ptr,
+                                                       int32_t* __restrict__ unit_ptr,
+                                                       int32_t* __restrict__ block_sums) {
+    __shared__ int32_t sh[1024];
+    const int i = (int)(blockIdx.x * 1024 + threadIdx.x);
+    int32_t v = 0;
+    if (i < n) {
+        const int32_t len = row_ptr[i + 1] - row_ptr[i];
+        v = len > 0 ? (len + 63) / 64 : 1;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele
+        const int32_t t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) unit_ptr[i] = sh[threadIdx.x] - v;  // exclusive within the block
+    if (threadIdx.x == 1023) block_sums[blockIdx.x] = sh[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_units_top(int nb, int32_t* __restrict__ block_sums,
+                                                     int32_t* __restrict__ total) {
+    // one block: exclusive scan of nb block sums, 1024-wide pieces in order
+    __shared__ int32_t sh[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int32_t v = i < nb ? block_sums[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int32_t t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) block_sums[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_units_add(int n, int32_t* __restrict__ unit_ptr,
+                                                     const int32_t* __restrict__ block_sums,
+                                                     const int32_t* __restrict__ total) {
+    const int i = (int)(blockIdx.x * 1024 + threadIdx.x);
+    if (i < n) unit_ptr[i] += block_sums[blockIdx.x];
+    if (i == 0) unit_ptr[n] = *total;
+}
+
+__device__ __forceinline__ int64_t unit_base(const int32_t* row_ptr, const int32_t* unit_ptr,
+                                             int i) {
+    return (int64_t)(row_ptr[i] - row_ptr[0]) + unit_ptr[i];
+}
+
+// start unit of block b = first unit whose cost offset is >= b*D
+__global__ void k_partition(int n, int nb, int D, const int32_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ unit_ptr, int32_t* __restrict__ srow,
+                            int32_t* __restrict__ sunit) {
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b > nb) return;
+    const int64_t target = (int64_t)b * D;
+    // largest row i with base_i <= target (base is nondecreasing, base_0 = 0)
+    int lo = 0, hi = n;  // answer in [0, n]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (unit_base(row_ptr, unit_ptr, mid) <= target) lo = mid; else hi = mid - 1;
+    }
+    int i = lo;
+    int32_t j = 0;
+    if (i < n) {
+        const int64_t base = unit_base(row_ptr, unit_ptr, i);
+        const int32_t nu = unit_ptr[i + 1] - unit_ptr[i];
+        const int64_t jj = (target - base + 64) / 65;  // ceil((target - base) / 65)
+        if (jj >= nu) {
+            i += 1;
+            j = 0;
+        } else {
+            j = (int32_t)jj;
+        }
+    }
+    if (b == nb) {
+        i = n;
+        j = 0;
+    }
+    srow[b] = i;
+    sunit[b] = j;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y,
+                                                  const int32_t* __restrict__ srow,
+                                                  const int32_t* __restrict__ sunit,
+                                                  const int32_t* __restrict__ unit_ptr,
+                                                  double* __restrict__ unit_sums) {
+    constexpr int D = 4 * B;
+    // a unit that starts just below the block's cost limit may extend 64
+    // leaves past it: at most D + 64 leaves and D rows per block
+    __shared__ double s[D + 64];
+    __shared__ int32_t rs[D + 2];  // row starts (global nnz offsets) of the block's rows
+    const int b = (int)blockIdx.x;
+    const int i0 = srow[b], j0 = sunit[b], i1 = srow[b + 1], j1 = sunit[b + 1];
+    const int32_t e0 = (i0 < n ? row_ptr[i0] : row_ptr[n]) + 64 * j0;
+    int32_t e1 = (i1 < n ? row_ptr[i1] : row_ptr[n]) + 64 * j1;
+    if (i1 < n) e1 = min(e1, row_ptr[i1 + 1]);
+    const int cnt = e1 - e0;                     // <= D + 64
+    const int ilast = (j1 > 0) ? i1 : i1 - 1;    // last row touched
+    const int nrows = ilast - i0 + 1;            // <= D
+    for (int t = (int)threadIdx.x; t <= nrows && t < D + 2; t += B) rs[t] = row_ptr[i0 + t];
+    for (int p = (int)threadIdx.x; p < cnt; p += B) {
+        const int64_t k = (int64_t)e0 + p;
+        s[p] = val[k] * x[col[k]];
+    }
+    __syncthreads();
+    // canonical tree inside each 64-leaf unit
+    for (int d = 1; d < 64; d <<= 1) {
+        for (int p = (int)threadIdx.x; p < cnt; p += B) {
+            const int32_t g = e0 + p;
+            int lo = 0, hi = nrows - 1;  // row t with rs[t] <= g < rs[t + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rs[mid] <= g) lo = mid; else hi = mid - 1;
+            }
+            const int32_t r = g - rs[lo];
+            const int32_t q = r & 63;
+            const int32_t len = rs[lo + 1] - rs[lo];
+            if ((q & (2 * d - 1)) == 0 && q + d < 64 && r + d < len) s[p] = s[p] + s[p + d];
+        }
+        __syncthreads();
+    }
+    // rows: complete ones are finished here, split ones leave their unit sums
+    for (int t = (int)threadIdx.x; t < nrows; t += B) {
+        const int i = i0 + t;
+        const int32_t rb = rs[t], re = rs[t + 1];
+        const int32_t nu = re > rb ? (re - rb + 63) / 64 : 1;
+        const int32_t ja = (t == 0) ? j0 : 0;
+        const int32_t jb = (i == i1) ? j1 : nu;  // units [ja, jb) are in this block
+        const bool whole = (ja == 0) && (i < i1);
+        if (whole) {
+            Counter c;
+            for (int32_t j = ja; j < jb; ++j) {
+                const int32_t g = rb + 64 * j;
+                if (g < re) c.push(s[g - e0]);
+            }
+            y[i] = c.finish();
+        } else {
+            for (int32_t j = ja; j < jb; ++j) {
+                const int32_t g = rb + 64 * j;
+                unit_sums[unit_ptr[i] + j] = (g < re) ? s[g - e0] : 0.0;
+            }
+        }
+    }
+}
+
+// one thread per block boundary: the first boundary inside a row finishes it
+__global__ void k_merge_fixup(int nb, const int32_t* __restrict__ row_ptr,
+                              const int32_t* __restrict__ srow, const int32_t* __restrict__ sunit,
+                              const int32_t* __restrict__ unit_ptr,
+                              const double* __restrict__ unit_sums, double* __restrict__ y) {
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b <= 0 || b >= nb) return;
+    if (sunit[b] == 0) return;
+    const int i = srow[b];
+    if (srow[b - 1] == i && sunit[b - 1] > 0) return;  // an earlier boundary splits this row
+    Counter c;
+    const int32_t len = row_ptr[i + 1] - row_ptr[i];
+    const int32_t nu = (len + 63) / 64;
+    for (int32_t j = 0; j < nu; ++j) c.push(unit_sums[unit_ptr[i] + j]);
+    y[i] = c.finish();
+}
+
+}  // namespace
+
+hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s) {
+    const int D = 4 * B;
+    for (const auto& m : p.mp)
+        if (m.D == D) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (!p.unit_ptr) {
+        const int nblk = (p.n + 1023) / 1024;
+        int32_t* bs = nullptr;
+        e = hipMalloc(&p.unit_ptr, ((size_t)p.n + 1) * 4);
+        if (e == hipSuccess) e = hipMalloc(&bs, ((size_t)nblk + 1) * 4);
+        if (e != hipSuccess) {
+            if (bs) hipFree(bs);
+            return e;
+        }
+        hipLaunchKernelGGL(k_units_block, dim3(nblk), dim3(1024), 0, s, p.n, p.row_ptr, p.unit_ptr,
+                           bs);
+        hipLaunchKernelGGL(k_units_top, dim3(1), dim3(1024), 0, s, nblk, bs, bs + nblk);
+        hipLaunchKernelGGL(k_units_add, dim3(nblk), dim3(1024), 0, s, p.n, p.unit_ptr, bs,
+                           bs + nblk);
+        e = hipGetLastError();
+        int32_t total = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, p.unit_ptr + p.n, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(bs);
+        if (e != hipSuccess) return e;
+        p.units = total;
+        e = hipMalloc(&p.unit_sums, (size_t)std::max<int64_t>(p.units, 1) * 8);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t cost = p.nnz + p.units;
+    const int64_t nb = (cost + D - 1) / D;
+    if (nb > 0x7ffffffe) return hipErrorInvalidConfiguration;
+    SpmvPlan::MergeSplit m;
+    m.D = D;
+    m.blocks = (int)std::max<int64_t>(nb, 1);
+    e = hipMalloc(&m.srow, ((size_t)m.blocks + 1) * 8);
+    if (e != hipSuccess) return e;
+    m.sunit = m.srow + m.blocks + 1;
+    hipLaunchKernelGGL(k_partition, dim3((m.blocks + 256) / 256), dim3(256), 0, s, p.n, m.blocks,
+                       D, p.row_ptr, p.unit_ptr, m.srow, m.sunit);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFree(m.srow);
+        return e;
+    }
+    p.mp.push_back(m);
+    return hipSuccess;
+}
+
+hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
+                           const double* x, double* y, hipStream_t s) {
+    const int B = v.bx;
+    const SpmvPlan::MergeSplit* m = nullptr;
+    for (const auto& q : p.mp)
+        if (q.D == 4 * B) m = &q;
+    if (!m) return hipErrorNotReady;  // plan not prepared (the runtime prepares it)
+    switch (B) {
+#define AO_MP(BB)                                                                           \
+    case BB:                                                                                \
+        hipLaunchKernelGGL(k_merge_path<BB>, dim3(m->blocks), dim3(BB), 0, s, p.n, p.row_ptr, \
+                           col, val, x, y, m->srow, m->sunit, p.unit_ptr, p.unit_sums);     \
+        break;
+        AO_MP(64) AO_MP(128) AO_MP(256) AO_MP(512) AO_MP(1024)
+#undef AO_MP
+        default:
+            return hipErrorInvalidConfiguration;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_merge_fixup, dim3((m->blocks + 255) / 256), dim3(256), 0, s, m->blocks,
+                       p.row_ptr, m->srow, m->sunit, p.unit_ptr, p.unit_sums, y);
+    return hipGetLastError();
 }
 
 }  // namespace ao

@@ -126,7 +126,9 @@ def csr_structure(n_rows: int, n_cols: int, lengths: np.ndarray, seed: int):
     """row_ptr (int32, n_rows+1) and col (int32, nnz): row i holds lengths[i]
     distinct columns drawn uniformly from [0, n_cols), stored ascending.
     Duplicates within a row are redrawn from further sub-streams
-    (tags 16, 17, ...) until none remain."""
+    (tags 16, 17, ...) until none remain.  A row longer than n_cols / 4
+    instead takes the first lengths[i] columns of a random order of all
+    columns (SplitMix64 keys of sub-stream 15 xor the row index)."""
     lengths = np.asarray(lengths, dtype=np.int64)
     if lengths.size and int(lengths.max()) > n_cols:
         raise ValueError("a row cannot hold more distinct columns than the matrix has")
@@ -137,6 +139,9 @@ def csr_structure(n_rows: int, n_cols: int, lengths: np.ndarray, seed: int):
         raise ValueError("nnz must fit int32 indices")
     rows = np.repeat(np.arange(n_rows, dtype=np.int64), lengths)
     cols = np.floor(u01(substream(seed, 2), nnz) * n_cols).astype(np.int64)
+    for r in np.nonzero(lengths > n_cols // 4)[0]:
+        order = np.argsort(splitmix64(substream(seed, 15) ^ int(r), n_cols), kind="stable")
+        cols[row_ptr64[r]:row_ptr64[r + 1]] = order[:lengths[r]]
     key = rows * n_cols + cols
     key.sort()
     rnd = 0

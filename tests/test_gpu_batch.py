@@ -1,0 +1,90 @@
+"""Batched persistent execution of many uneven Jacobi instances: every
+instance bit-identical to a standalone region run (and to the oracle on
+small ones), before and after autotuning, eager and as a replayed graph."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2303_08873_amd as ao
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    return ao, torch, dev, torch.cuda.current_stream(dev)
+
+
+def _instances(ao, torch, dev, shapes, sweeps, seed0):
+    ins, bufs = [], []
+    for q, ((nx, ny, nz), s) in enumerate(zip(shapes, sweeps)):
+        u0 = synth.grid_u01_torch(int(nx), int(ny), int(nz), seed=seed0 + q, device=dev)
+        out = torch.full_like(u0, float("nan"))
+        bufs.append((u0, out))
+        ins.append(ao.jacobi_args(u0, out, int(nx), int(ny), int(nz), int(s)))
+    return ins, bufs
+
+
+def _reference(ao, torch, st, ins, bufs):
+    h = ao.region_declare_variants("batch_ref", ao.AO_JACOBI7_F64,
+                                   [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, 64, 4, 1, 0)],
+                                   model_type="roundrobin")
+    refs = []
+    for a, (u0, out) in zip(ins, bufs):
+        r = torch.empty_like(u0)
+        ra = ao.jacobi_args(u0, r, a.nx, a.ny, a.nz, a.sweeps)
+        ao.region_run(h, ra, stream=st, variant=0)
+        refs.append(r)
+    torch.cuda.synchronize()
+    return refs
+
+
+def _check(torch, bufs, refs, tag):
+    for q, ((u0, out), r) in enumerate(zip(bufs, refs)):
+        assert torch.equal(out, r), f"{tag}: instance {q} differs from its standalone run"
+
+
+def test_batch_small_mixed_against_oracle(env, orc):
+    ao, torch, dev, st = env
+    shapes = [(8, 8, 8), (5, 17, 3), (70, 9, 40), (1, 1, 30), (33, 65, 2), (130, 20, 11),
+              (16, 16, 16), (3, 200, 4)]
+    sweeps = [5, 1, 4, 3, 0, 2, 7, 5]
+    ins, bufs = _instances(ao, torch, dev, shapes, sweeps, 900)
+    b = ao.batch_create(ins)
+    ao.batch_run(b, stream=st, use_graph=False)
+    torch.cuda.synchronize()
+    for (u0, out), (nx, ny, nz), s in zip(bufs, shapes, sweeps):
+        want = orc.jacobi7(u0.cpu().numpy(), nx, ny, nz, s)
+        assert np.array_equal(out.cpu().numpy(), want), (nx, ny, nz, s)
+    ao.batch_destroy(b)
+
+
+def test_batch_256_uneven_graph_and_autotune(env):
+    # 256 grids, each dimension log-uniform in [8, 256] (seed 3), 5 sweeps
+    ao, torch, dev, st = env
+    shapes = synth.batch_shapes(256, 8, 256, seed=3)
+    ins, bufs = _instances(ao, torch, dev, shapes, [5] * 256, 3000)
+    refs = _reference(ao, torch, st, ins, bufs)
+    b = ao.batch_create(ins)
+    inst, items, tiles = ao.batch_info(b)
+    assert sum(inst) == 256 and all(i > 0 for i, c in zip(items, inst) if c > 0)
+    ao.batch_run(b, stream=st, use_graph=False)
+    torch.cuda.synchronize()
+    _check(torch, bufs, refs, "eager")
+    chosen = ao.batch_autotune(b, stream=st, warmup=1, reps=3)
+    assert all((c >= 0) == (n > 0) for c, n in zip(chosen, inst))
+    # graph replays with eager work in between, each replay checked
+    for rep in range(3):
+        for _, out in bufs:
+            out.fill_(float("nan"))
+        ao.batch_run(b, stream=st, use_graph=True)
+        torch.cuda.synchronize()
+        _check(torch, bufs, refs, f"graph replay {rep}")
+        junk = torch.ones(1 << 20, device=dev) * rep   # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    ao.batch_destroy(b)

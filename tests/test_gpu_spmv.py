@@ -1,0 +1,152 @@
+"""GPU parity of the SpMV region variants: every variant bit-identical to
+the canonical-order oracle (and within 1e-12 * sum|a x| of the plain
+left-to-right oracle), on Pareto-row matrices, empty and long rows, special
+matrices, and the full 2^22-row workload; the GPU row-length features
+against the oracle's."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2303_08873_amd as ao
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    return ao, torch, dev, torch.cuda.current_stream(dev)
+
+
+def _variants(ao):
+    vs = ao.spmv_variants(blocks=(64, 256, 1024))
+    for w in (1, 2, 4, 8, 16, 32):
+        vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_WAVE_ROW, 256, w, 1, 0))
+    for b in (128, 512):
+        vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, b, 0, 1, 0))
+    return vs
+
+
+def _run_all(ao, torch, dev, st, m, name):
+    n = m["row_ptr"].size - 1
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in m.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+    vs = _variants(ao)
+    outs = []
+    for c0 in range(0, len(vs), 12):
+        h = ao.region_declare_variants(f"{name}_{c0}", ao.AO_CSR_SPMV_F64, vs[c0:c0 + 12],
+                                       model_type="roundrobin")
+        for v in range(len(vs[c0:c0 + 12])):
+            y.fill_(float("nan"))
+            ao.region_run(h, a, stream=st, variant=v)
+            torch.cuda.synchronize()
+            outs.append((vs[c0 + v], y.cpu().numpy().copy()))
+        ao.region_destroy(h)
+    return outs
+
+
+def _check_all(outs, want, want_plain, scale):
+    for var, got in outs:
+        assert not np.any(np.isnan(got)), f"{var}: rows not written"
+        if not np.array_equal(got, want) or not np.array_equal(np.signbit(got), np.signbit(want)):
+            bad = int(np.sum(got != want))
+            pytest.fail(f"{var}: {bad} rows differ from the canonical oracle")
+        assert np.all(np.abs(got - want_plain) <= 1e-12 * scale), var
+
+
+def _scale(m):
+    """sum_k |val_k x_col_k| per row (the scale of the plain-order tolerance)."""
+    rp, col, val, x = m["row_ptr"], m["col"], m["val"], m["x"]
+    cs = np.concatenate([[0.0], np.cumsum(np.abs(val * x[col]))])
+    return cs[rp[1:].astype(np.int64)] - cs[rp[:-1].astype(np.int64)]
+
+
+@pytest.mark.parametrize("n,mean,max_len,seed", [(3000, 16.0, 300, 50), (700, 4.0, 700, 51),
+                                                 (5000, 64.0, 4096, 52), (257, 16.0, 257, 53)])
+def test_pareto_matrices(env, orc, n, mean, max_len, seed):
+    ao, torch, dev, st = env
+    m = synth.csr_matrix(n, seed, mean=mean, max_len=max_len)
+    want = orc.spmv_canonical(m["row_ptr"], m["col"], m["val"], m["x"])
+    plain = orc.spmv_plain(m["row_ptr"], m["col"], m["val"], m["x"])
+    _check_all(_run_all(ao, torch, dev, st, m, f"par{seed}"), want, plain, _scale(m))
+
+
+def test_empty_long_and_signed_zero_rows(env, orc):
+    ao, torch, dev, st = env
+    # rows: empty, 1, 64, 65, 4096 (ones), empty, 130, 7 (-0.0 products), empty
+    lens = [0, 1, 64, 65, 4096, 0, 130, 7, 0]
+    n = 5000
+    rp, col = synth.csr_structure(len(lens), n, np.array(lens), 61)
+    val = synth.normal_values(col.size, 61)
+    x = synth.dense_vector_pm1(n, 61)
+    s = rp[4]
+    col[s:s + 4096] = np.arange(4096)   # row 4: 4096 ones times ones
+    val[s:s + 4096] = 1.0
+    x[:4096] = 1.0
+    z0 = rp[7]
+    col[z0:z0 + 7] = np.arange(4096, 4103)
+    val[z0:z0 + 7] = -1.0
+    x[4096:4103] = 0.0                  # products -1 * +0 = -0.0 -> the row sums to -0.0
+    m = {"row_ptr": rp, "col": col, "val": val, "x": x}
+    # 9 rows over 5000 columns: x is longer than y
+    want = orc.spmv_canonical(rp, col, val, x)
+    assert want[4] == 4096.0 and np.signbit(want[7]) and want[0] == 0 and not np.signbit(want[0])
+    plain = orc.spmv_plain(rp, col, val, x)
+    _check_all(_run_all(ao, torch, dev, st, m, "edge"), want, plain, _scale(m))
+
+
+def test_special_matrices_exact(env, orc):
+    ao, torch, dev, st = env
+    n = 1000
+    x = synth.dense_vector_pm1(n, 71)
+    perm = np.argsort(synth.splitmix64(72, n)).astype(np.int32)
+    for name, col, val in (("ident", np.arange(n, dtype=np.int32), np.ones(n)),
+                           ("perm", perm, np.ones(n)),
+                           ("diag", np.arange(n, dtype=np.int32), 2.0 ** (np.arange(n) % 7 - 3))):
+        m = {"row_ptr": np.arange(n + 1, dtype=np.int32), "col": col, "val": val, "x": x}
+        for var, got in _run_all(ao, torch, dev, st, m, name):
+            assert np.array_equal(got, val * x[col]), (name, var)
+
+
+def test_features_match_oracle(env, orc):
+    ao, torch, dev, st = env
+    m = synth.csr_matrix(20000, 81, mean=16.0, max_len=4096)
+    n = 20000
+    t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    h = ao.region_declare_variants("feat", ao.AO_CSR_SPMV_F64, ao.spmv_variants()[:1],
+                                   model_type="roundrobin")
+    ao.region_run(h, ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n,
+                                  int(m["col"].size)), stream=st)
+    f, _, _ = ao.region_records(h)
+    want = orc.csr_features(m["row_ptr"])
+    assert np.allclose(np.array(f[0][:5]), want, rtol=1e-6, atol=0)
+    assert f[0][5] == 0.0
+    ao.region_destroy(h)
+
+
+def test_full_size_2_22(env, orc):
+    # n = 2^22 rows, Pareto tail 1.5, mean 16, max 4096, seed 5: all variants
+    # bit-identical to the canonical oracle on every row
+    ao, torch, dev, st = env
+    m = synth.csr_matrix(1 << 22, 5)
+    want = orc.spmv_canonical(m["row_ptr"], m["col"], m["val"], m["x"])
+    n = 1 << 22
+    t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    h = ao.region_declare_variants("full22", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
+                                   model_type="roundrobin")
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+    for v in range(9):
+        y.fill_(float("nan"))
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        assert np.array_equal(got, want), f"variant {v}: {int(np.sum(got != want))} rows differ"
+    ao.region_destroy(h)
