@@ -33,17 +33,85 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline():
-    """The serial C oracle timed on a bounded sample of the workload."""
+def cpu_baseline(repeats=2):
+    """The serial C oracle on the same inputs: the whole size sweep (every
+    grid, 20 sweeps) `repeats` times, one core."""
     import oracle
     import synth
-    n, s = 256, 6
-    u0 = synth.grid_u01(n, n, n, seed=2008)
+    grids = {n: synth.grid_u01(n, n, n, seed=2000 + int(math.log2(n))) for n in SIZES}
     t0 = time.perf_counter()
-    oracle.jacobi7(u0, n, n, n, s)
+    for _ in range(repeats):
+        for n in SIZES:
+            oracle.jacobi7(grids[n], n, n, n, SWEEPS)
     dt = time.perf_counter() - t0
-    return {"value": 16.0 * n ** 3 * s / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"serial C oracle, one {n}^3 grid x {s} sweeps ({dt:.1f} s)"}
+    total = repeats * sum(16.0 * n ** 3 * SWEEPS for n in SIZES)
+    return {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"serial C oracle, the full size sweep (16^3..512^3 x 20 sweeps) x {repeats} "
+                      f"({dt:.1f} s)"}
+
+
+def pmc_traffic(variant_key):
+    """HBM bytes per launch of the dominant kernel from the committed
+    counter summary (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the
+    copy-probe calibration), when it was taken for this kernel."""
+    path = os.path.join(ROOT, "profiles", "jacobi_512_pmc.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("variant") != variant_key:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def copy_probe(ao, torch, dev, stream, n=512 ** 3, reps=20):
+    """Achievable HBM bandwidth: the library's plain FP64 copy of n doubles."""
+    a = synth_u01(torch, dev, n)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        ao.ao_hbm_copy(a, b, n, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ao.ao_hbm_copy(a, b, n, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 16.0 * n / (ms * 1e-3) / 1e9
+
+
+def synth_u01(torch, dev, n):
+    import synth
+    return synth.u01_torch(4242, n, dev)
+
+
+def kernel_only(variant: int, launches: int = 3):
+    """Counter runs: the size-sweep variant `variant` at 512^3 x 20 sweeps,
+    `launches` region executions, then 5 copies of 512^3 doubles (the
+    calibration kernel of known traffic)."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = SIZES[-1]
+    region = ao.region_declare_variants("bench_kernel_only", ao.AO_JACOBI7_F64,
+                                        ao.jacobi_variants_sweep(), model_type="roundrobin")
+    u0 = synth.grid_u01_torch(n, n, n, seed=2000 + int(math.log2(n)), device=dev)
+    out = torch.empty_like(u0)
+    a = ao.jacobi_args(u0, out, n, n, n, SWEEPS)
+    for _ in range(launches):
+        ao.region_run(region, a, stream=stream, variant=variant)
+    torch.cuda.synchronize()
+    b = torch.empty_like(u0)
+    for _ in range(5):
+        ao.ao_hbm_copy(u0, b, n ** 3, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": variant, "launches": launches * SWEEPS, "copies": 5,
+                      "copy_bytes_each": 16 * n ** 3}), flush=True)
 
 
 def main():
@@ -52,7 +120,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", type=int, default=None,
+                    help="counter-collection mode: run one size-sweep variant at 512^3 only")
     args = ap.parse_args()
+    if args.kernel_only is not None:
+        kernel_only(args.kernel_only)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
                           "sharding of the region is a design, not a measured path",
@@ -120,6 +193,7 @@ def main():
     for ev in evs:
         big_ms.append(ev[0].elapsed_time(ev[1]))
 
+    copy_gbs = copy_probe(ao, torch, dev, stream)
     total_bytes = sum(16.0 * n ** 3 * SWEEPS for n in SIZES)
     value = total_bytes * args.steps / dt / 1e9
     best = {n: min(range(V), key=lambda v: table[n][v]) for n in SIZES}
@@ -130,6 +204,9 @@ def main():
     nbig = SIZES[-1]
     per_launch_ms = sorted(big_ms)[len(big_ms) // 2] / SWEEPS
     achieved = 16.0 * nbig ** 3 / (per_launch_ms * 1e-3) / 1e9
+    vbig = ao.jacobi_variants_sweep()[chosen[nbig]]
+    vkey = f"family={vbig.family} bx={vbig.bx} by={vbig.by} bz={vbig.bz} flags={vbig.flags}"
+    traffic = pmc_traffic(vkey)
     res = {
         "metric": "region GB/s (% HBM peak): learned vs exhaustive selection; selector regret %",
         "value": round(value, 2),
@@ -148,6 +225,8 @@ def main():
                                "(5 GPU shapes + 5 host-CPU tilings)",
                    "sizes": SIZES, "sweeps": SWEEPS},
         "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "largest_size_pct_of_copy_probe": None,
         "exhaustive_gbs": round(total_bytes / t_best / 1e9, 2),
         "learned_gbs_from_table": round(total_bytes / t_sel / 1e9, 2),
         "regret_pct": round(100.0 * (t_sel / t_best - 1.0), 3),
@@ -156,10 +235,12 @@ def main():
         "exhaustive_best": {str(n): best[n] for n in SIZES},
         "largest_size_gbs": round(16.0 * nbig ** 3 * SWEEPS / (sorted(big_ms)[len(big_ms) // 2] * 1e-3) / 1e9, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"variant {chosen[nbig]} sweep at {nbig}^3",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": f"variant {chosen[nbig]} ({vkey}) sweep at {nbig}^3",
+                     "algorithmic_bytes_per_launch": 16 * nbig ** 3,
                      "per_launch_us": round(per_launch_ms * 1e3, 2)},
     }
+    res["largest_size_pct_of_copy_probe"] = round(100.0 * res["largest_size_gbs"] / copy_gbs, 2)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)

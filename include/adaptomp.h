@@ -179,7 +179,7 @@ int region_profile(ao_region* r, const ao_args* a, const float* features, int va
 
 /* Training options (NULL = defaults in brackets). */
 typedef struct ao_train_opts {
-    int32_t epochs;     /* [200] */
+    int32_t epochs;     /* [200]; 0 installs the untrained (initial) network */
     int32_t batch;      /* [256] */
     float lr;           /* [1e-3] Adam learning rate; betas 0.9 / 0.999, eps 1e-8 */
     uint64_t seed;      /* [7] SplitMix64 seed of the init and of the shuffles */

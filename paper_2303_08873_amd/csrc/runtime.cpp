@@ -671,7 +671,7 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
     harvest(r, true);
     ao_train_opts o{200, 256, 1e-3f, 7};
     if (opts) o = *opts;
-    if (o.epochs <= 0 || o.batch <= 0 || !(o.lr > 0.0f))
+    if (o.epochs < 0 || o.batch <= 0 || !(o.lr > 0.0f))
         return fail(AO_EINVAL, "bad training options");
     // merge duplicate (features, variant) samples by median, first-seen order
     std::unordered_map<UKey, size_t, UKeyHash> idx;
@@ -731,7 +731,7 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
         Y[i] = (float)(lt[i] - ymean);
     }
     // epoch shuffles: indices ordered by SplitMix64 keys (stable on ties)
-    std::vector<int32_t> perm((size_t)o.epochs * n);
+    std::vector<int32_t> perm(std::max<size_t>((size_t)o.epochs * n, 1));
     std::vector<std::pair<uint64_t, int32_t>> keyed(n);
     for (int e = 0; e < o.epochs; ++e) {
         const uint64_t es = splitmix_mix(((o.seed << 8) | (uint64_t)(e & 0xFF))) ^ (uint64_t)(e >> 8);
@@ -774,7 +774,7 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
     if (e == hipSuccess) e = hipMalloc(&dV, (size_t)n * 4);
     if (e == hipSuccess) e = hipMalloc(&dPerm, perm.size() * 4);
     if (e == hipSuccess) e = hipMalloc(&dP, AO_MLP_PARAMS * 4);
-    if (e == hipSuccess) e = hipMalloc(&dL, (size_t)o.epochs * 4);
+    if (e == hipSuccess) e = hipMalloc(&dL, (size_t)std::max(o.epochs, 1) * 4);
     if (e == hipSuccess) e = hipMalloc(&dMV, (size_t)2 * AO_MLP_PARAMS * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dY, Y.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
@@ -783,12 +783,12 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
         e = hipMemcpyAsync(dPerm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dP, theta.data(), AO_MLP_PARAMS * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && o.epochs > 0)
         e = mlp_train_launch(dP, dX, dY, dV, dPerm, n, o.epochs, o.batch, o.lr, dMV, dL, s);
-    std::vector<float> losses(o.epochs);
+    std::vector<float> losses(std::max(o.epochs, 1), NAN);
     if (e == hipSuccess)
         e = hipMemcpyAsync(theta.data(), dP, AO_MLP_PARAMS * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && o.epochs > 0)
         e = hipMemcpyAsync(losses.data(), dL, (size_t)o.epochs * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -799,7 +799,7 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
     cleanup();
     bool finite = true;
     for (float v : theta) finite = finite && std::isfinite(v);
-    if (!finite || !std::isfinite(losses.back())) {
+    if (!finite || (o.epochs > 0 && !std::isfinite(losses.back()))) {
         r->trained = false;
         return fail(AO_ESTATE, "training diverged (non-finite weights); model not installed");
     }

@@ -1,0 +1,163 @@
+"""Learned-selector evaluation of the Jacobi region (one GPU).
+
+Training data come from the method itself: a region with the 10 size-sweep
+variants runs every training shape once per variant under RoundRobin
+exploration (Sec. 2 Apollo paragraph), each run profiled.  The cost model
+is trained on those records by the library's GPU kernels.  Held-out shapes
+are timed exhaustively (every variant, warmup + repetitions, median) -- the
+table that defines the best variant and every regret below.  Compared:
+the learned selector, the static default (64x4 = 256-thread direct kernel,
+the OpenMP offload default team size, Sec. 4 "GPU threads"), and the
+untrained network.  Selection cost: the measured latency of a cold
+selector_select against the exhaustive selector's cost sum_v t_v.
+
+Usage: python -m paper_2303_08873_amd.evaluate [--train 2000] [--test 2000]
+       [--out results.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def _log(msg):
+    print(f"[evaluate] {msg}", file=sys.stderr, flush=True)
+
+
+def _stats(t_sel, t_best):
+    r = t_sel / t_best
+    return {"geomean_regret_pct": float((np.exp(np.mean(np.log(r))) - 1) * 100),
+            "mean_regret_pct": float((np.mean(r) - 1) * 100),
+            "p95_regret_pct": float((np.percentile(r, 95) - 1) * 100),
+            "hit_rate": float(np.mean(r <= 1.0 + 1e-12)),
+            "aggregate_regret_pct": float((t_sel.sum() / t_best.sum() - 1) * 100)}
+
+
+def run(n_train=2000, n_test=2000, train_seed=4, test_seed=40, max_dim=512, warmup=1, reps=5,
+        epochs=200, out=None):
+    import torch
+
+    import synth
+
+    from . import _lib as ao
+    from .variants import STATIC_DEFAULT, jacobi_variants_sweep
+
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    V = 10
+    nmax = max_dim ** 3
+    # one buffer pair per residency, sized for the largest shape; every
+    # shape uses a prefix (values U[0,1) from seed 4242)
+    u0_d = synth.u01_torch(4242, nmax, dev)
+    out_d = torch.empty_like(u0_d)
+    u0_h = torch.empty(nmax, dtype=torch.float64).pin_memory()
+    u0_h.copy_(u0_d)
+    out_h = torch.empty(nmax, dtype=torch.float64).pin_memory()
+    torch.cuda.synchronize()
+
+    def args_for(d, s, res):
+        nx, ny, nz = (int(v) for v in d)
+        if res:
+            return ao.jacobi_args(u0_d, out_d, nx, ny, nz, int(s), 1)
+        return ao.jacobi_args(u0_h, out_h, nx, ny, nz, int(s), 0)
+
+    region = ao.region_declare_variants(f"eval_{train_seed}_{n_train}", ao.AO_JACOBI7_F64,
+                                        jacobi_variants_sweep(), min_train_data=10 ** 9,
+                                        model_type="mlp")
+    dims, sw, res = synth.selector_shapes(n_train, train_seed, hi=max_dim)
+    t0 = time.perf_counter()
+    for q in range(n_train):
+        a = args_for(dims[q], sw[q], res[q])
+        for _ in range(V):
+            ao.region_run(region, a, stream=st)
+        if (q + 1) % 200 == 0:
+            torch.cuda.synchronize()
+            _log(f"training runs: {(q + 1) * V} ({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    collect_s = time.perf_counter() - t0
+    stats0 = ao.region_stats(region)
+
+    # held-out exhaustive table
+    tdims, tsw, tres = synth.selector_shapes(n_test, test_seed, hi=max_dim)
+    table = np.zeros((n_test, V))
+    feats = []
+    t0 = time.perf_counter()
+    for q in range(n_test):
+        a = args_for(tdims[q], tsw[q], tres[q])
+        table[q] = ao.region_profile(region, a, warmup=warmup, reps=reps, stream=st, num_variants=V)
+        n = int(np.prod(tdims[q]))
+        b = 16.0 * n * int(tsw[q])
+        feats.append([math.log2(int(tdims[q][0])), math.log2(int(tdims[q][1])),
+                      math.log2(int(tdims[q][2])), float(tsw[q]), math.log2(b), float(tres[q])])
+        if (q + 1) % 200 == 0:
+            _log(f"exhaustive table: {q + 1} shapes ({time.perf_counter() - t0:.0f} s)")
+    table_s = time.perf_counter() - t0
+    best = table.argmin(axis=1)
+    t_best = table[np.arange(n_test), best]
+
+    result = {"train_shapes": n_train, "test_shapes": n_test, "variants": V,
+              "train_records": int(stats0.records), "train_unique": int(stats0.unique),
+              "collect_seconds": collect_s, "table_seconds": table_s,
+              "table_protocol": f"warmup {warmup}, median of {reps}",
+              "best_variant_histogram": np.bincount(best, minlength=V).tolist()}
+
+    # untrained network (initial weights, normalisation from the data)
+    ao.selector_train(region, epochs=0)
+    _, ids_u = ao.selector_select(region, feats)
+    ids_u = np.array(ids_u)
+    # trained network
+    t0 = time.perf_counter()
+    loss = ao.selector_train(region, epochs=epochs)
+    train_wall = time.perf_counter() - t0
+    _, ids = ao.selector_select(region, feats)
+    ids = np.array(ids)
+    # cold single-vector selection latency (no memo in selector_select)
+    lat = []
+    for f in feats[:min(n_test, 500)]:
+        t1 = time.perf_counter()
+        ao.selector_select(region, [f])
+        lat.append(time.perf_counter() - t1)
+    lat = np.array(lat)
+    exh_cost = table.sum(axis=1)[:lat.size]
+
+    idx = np.arange(n_test)
+    result.update({
+        "train_final_loss": loss, "train_seconds": train_wall,
+        "train_kernel_seconds": ao.region_stats(region).last_train_seconds,
+        "learned": _stats(table[idx, ids], t_best),
+        "static_default": _stats(table[:, STATIC_DEFAULT], t_best),
+        "untrained_net": _stats(table[idx, ids_u], t_best),
+        "selection_latency_us_median": float(np.median(lat) * 1e6),
+        "exhaustive_cost_us_median": float(np.median(exh_cost) * 1e6),
+        "selection_cost_ratio_median": float(np.median(exh_cost / lat)),
+        "selection_cost_ratio_with_protocol_median": float(np.median(exh_cost * (warmup + reps) / lat)),
+        "learned_hist": np.bincount(ids, minlength=V).tolist(),
+    })
+    _log(json.dumps(result))
+    if out:
+        with open(out, "w") as fh:
+            json.dump(result, fh, indent=1)
+    ao.region_destroy(region)
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=2000)
+    ap.add_argument("--max-dim", type=int, default=512)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    r = run(a.train, a.test, max_dim=a.max_dim, reps=a.reps, epochs=a.epochs, out=a.out)
+    print(json.dumps(r))
+
+
+if __name__ == "__main__":
+    main()

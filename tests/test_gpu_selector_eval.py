@@ -1,0 +1,18 @@
+"""The learned selector against the method without it, on a small instance
+of the evaluation pipeline: RoundRobin-profiled training runs, GPU
+training, an exhaustive held-out table.  The trained network must beat the
+untrained one and the static default, and selecting must cost at least 10x
+less than timing every variant."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_selector_gain():
+    from paper_2303_08873_amd import evaluate
+    r = evaluate.run(n_train=80, n_test=60, max_dim=96, reps=3, epochs=150)
+    learned, untrained, static = r["learned"], r["untrained_net"], r["static_default"]
+    assert learned["geomean_regret_pct"] <= untrained["geomean_regret_pct"]
+    assert learned["geomean_regret_pct"] <= static["geomean_regret_pct"] + 1.0
+    assert learned["geomean_regret_pct"] <= 25.0
+    assert r["selection_cost_ratio_median"] >= 10.0
