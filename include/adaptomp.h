@@ -84,7 +84,8 @@ enum ao_family {
 };
 
 /* variant flags */
-#define AO_VF_NT_STORE 1 /* non-temporal (streaming) stores of the output */
+#define AO_VF_NT_STORE 1      /* non-temporal (streaming) stores of the output */
+#define AO_VF_HALO_PREFETCH 2 /* register z-march: load the next plane's halo a plane ahead */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,

@@ -22,7 +22,9 @@
 //          iteration k), the x-neighbours come from the adjacent lanes by
 //          cross-lane moves (the two strip edges are loaded by lanes 0 and
 //          63), the y-neighbours from the wave's own rows plus two halo rows.
-//          A block is 4 such waves stacked in y (tile 64*VX x 4R).
+//          A block is 4 such waves stacked in y (tile 64*VX x 4R).  With the
+//          halo-prefetch flag the halo of plane k+1 is also loaded during
+//          plane k, so no iteration waits on its own loads.
 //
 // All map blockIdx.x to tiles XCD-aware: the hardware deals workgroups to
 // the 8 XCDs round-robin, so consecutive logical tiles (which share z- and
@@ -157,7 +159,7 @@ __device__ __forceinline__ Vec<VX> load_row(const double* __restrict__ row, int 
     return r;
 }
 
-template <int R, int VX, bool NT>
+template <int R, int VX, bool NT, bool PF>
 __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __restrict__ src,
                                                              double* __restrict__ dst, int nx,
                                                              int ny, int nz, int nbx, int nby,
@@ -180,10 +182,24 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
     // edge lanes fetch the neighbour just outside the strip
     const int ie = (lane == 0) ? i0 - 1 : i0 + TW;
     const bool edge = (lane == 0 && i0 > 0) || (lane == 63 && i0 + TW < nx);
+    auto row_ptr = [&](int k, int j) { return src + (size_t)k * plane + (size_t)j * nx; };
+    // in-plane halo of plane k: rows j0-1 and j0+R, and the two strip edges
+    struct Halo {
+        Vec<VX> ym, yp;
+        double ex[R];
+    };
+    auto load_halo = [&](int k, Halo& h) {
+        const bool ok = k < nz;
+        h.ym = load_row<VX>(row_ptr(min(k, nz - 1), max(j0 - 1, 0)), i, nx, ok && j0 > 0);
+        h.yp = load_row<VX>(row_ptr(min(k, nz - 1), min(j0 + R, ny - 1)), i, nx, ok && j0 + R < ny);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool okj = j0 + r < ny;
+            h.ex[r] = (ok && edge && okj) ? row_ptr(min(k, nz - 1), min(j0 + r, ny - 1))[ie] : 0.0;
+        }
+    };
 
     Vec<VX> below[R], cur[R], above[R];
-    double ex[R];
-    auto row_ptr = [&](int k, int j) { return src + (size_t)k * plane + (size_t)j * nx; };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const bool okj = j0 + r < ny;
@@ -191,15 +207,19 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
                                 okj && k0 > 0);
         cur[r] = load_row<VX>(row_ptr(k0, min(j0 + r, ny - 1)), i, nx, okj);
     }
+    Halo hc;
+    if constexpr (PF) load_halo(k0, hc);
     for (int k = k0; k < k1; ++k) {
         const bool has_up = k + 1 < nz;
-        const Vec<VX> ym_row = load_row<VX>(row_ptr(k, max(j0 - 1, 0)), i, nx, j0 > 0);
-        const Vec<VX> yp_row = load_row<VX>(row_ptr(k, min(j0 + R, ny - 1)), i, nx, j0 + R < ny);
+        Halo hn;
+        if constexpr (PF) {
+            load_halo(k + 1, hn);  // consumed next iteration
+        } else {
+            load_halo(k, hc);      // consumed now
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const bool okj = j0 + r < ny;
-            const double* rp = row_ptr(k, min(j0 + r, ny - 1));
-            ex[r] = (edge && okj) ? rp[ie] : 0.0;
             above[r] = load_row<VX>(has_up ? row_ptr(k + 1, min(j0 + r, ny - 1)) : src, i, nx,
                                     okj && has_up);
         }
@@ -209,14 +229,14 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
             // x neighbours: within the lane, then across lanes
             const double left = __shfl_up(cur[r].v[VX - 1], 1);
             const double right = __shfl_down(cur[r].v[0], 1);
-            const double xl = (lane == 0) ? ex[r] : left;
-            const double xr = (lane == 63) ? ex[r] : right;
+            const double xl = (lane == 0) ? hc.ex[r] : left;
+            const double xr = (lane == 63) ? hc.ex[r] : right;
 #pragma unroll
             for (int q = 0; q < VX; ++q) {
                 const double xm = (q == 0) ? xl : cur[r].v[q - 1];
                 const double xp = (q == VX - 1) ? xr : cur[r].v[q + 1];
-                const double ym = (r == 0) ? ym_row.v[q] : cur[r - 1].v[q];
-                const double yp = (r == R - 1) ? yp_row.v[q] : cur[r + 1].v[q];
+                const double ym = (r == 0) ? hc.ym.v[q] : cur[r - 1].v[q];
+                const double yp = (r == R - 1) ? hc.yp.v[q] : cur[r + 1].v[q];
                 double v = xm + xp;
                 v = v + ym;
                 v = v + yp;
@@ -231,18 +251,26 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
             below[r] = cur[r];
             cur[r] = above[r];
         }
+        if constexpr (PF) hc = hn;
     }
 }
 
 template <int R, int VX>
-hipError_t launch_zreg(bool nt, dim3 grid, hipStream_t s, const double* src, double* dst, int nx,
-                       int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
-    if (nt)
-        hipLaunchKernelGGL((jac_zreg<R, VX, true>), grid, dim3(64 * kZregWaves), 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
+hipError_t launch_zreg(bool nt, bool pf, dim3 grid, hipStream_t s, const double* src, double* dst,
+                       int nx, int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
+    const dim3 block(64 * kZregWaves);
+    if (nt && pf)
+        hipLaunchKernelGGL((jac_zreg<R, VX, true, true>), grid, block, 0, s, src, dst, nx, ny, nz,
+                           nbx, nby, bz, nb);
+    else if (nt)
+        hipLaunchKernelGGL((jac_zreg<R, VX, true, false>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
+    else if (pf)
+        hipLaunchKernelGGL((jac_zreg<R, VX, false, true>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     else
-        hipLaunchKernelGGL((jac_zreg<R, VX, false>), grid, dim3(64 * kZregWaves), 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg<R, VX, false, false>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     return hipGetLastError();
 }
 
@@ -310,6 +338,7 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
     if (v.family == AO_FAM_JACOBI_ZREG) {
         // bx = strip width (64 or 128 points), by = rows per wave, bz = planes
         const int VX = bx / 64, R = by, bz = v.bz;
+        const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
         if ((bx != 64 && bx != 128) || bz <= 0) return hipErrorInvalidConfiguration;
         if (VX == 2 && ((nx & 1) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)))
             return hipErrorInvalidConfiguration;
@@ -320,7 +349,7 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
         const unsigned u = (unsigned)nb;
 #define AO_ZREG(RR, VV)                                                                  \
     if (R == RR && VX == VV)                                                             \
-        return launch_zreg<RR, VV>(nt, grid, s, src, dst, nx, ny, nz, nbxz, nbyz, bz, u);
+        return launch_zreg<RR, VV>(nt, pf, grid, s, src, dst, nx, ny, nz, nbxz, nbyz, bz, u);
         AO_ZREG(1, 1) AO_ZREG(2, 1) AO_ZREG(4, 1) AO_ZREG(8, 1)
         AO_ZREG(1, 2) AO_ZREG(2, 2) AO_ZREG(4, 2) AO_ZREG(8, 2)
 #undef AO_ZREG

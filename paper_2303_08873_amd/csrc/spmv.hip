@@ -372,24 +372,43 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
     const int ilast = (j1 > 0) ? i1 : i1 - 1;    // last row touched
     const int nrows = ilast - i0 + 1;            // <= D
     for (int t = (int)threadIdx.x; t <= nrows && t < D + 2; t += B) rs[t] = row_ptr[i0 + t];
-    for (int p = (int)threadIdx.x; p < cnt; p += B) {
-        const int64_t k = (int64_t)e0 + p;
-        s[p] = val[k] * x[col[k]];
+    constexpr int E = 4 + (64 + B - 1) / B;  // leaves per thread: ceil((D + 64) / B)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = (int)threadIdx.x + e * B;
+        if (p < cnt) {
+            const int64_t k = (int64_t)e0 + p;
+            s[p] = val[k] * x[col[k]];
+        }
     }
     __syncthreads();
-    // canonical tree inside each 64-leaf unit
-    for (int d = 1; d < 64; d <<= 1) {
-        for (int p = (int)threadIdx.x; p < cnt; p += B) {
+    // each leaf's position r in its row and the row length, found once
+    int32_t rr[E], ln[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = (int)threadIdx.x + e * B;
+        rr[e] = -1;
+        ln[e] = 0;
+        if (p < cnt) {
             const int32_t g = e0 + p;
             int lo = 0, hi = nrows - 1;  // row t with rs[t] <= g < rs[t + 1]
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (rs[mid] <= g) lo = mid; else hi = mid - 1;
             }
-            const int32_t r = g - rs[lo];
-            const int32_t q = r & 63;
-            const int32_t len = rs[lo + 1] - rs[lo];
-            if ((q & (2 * d - 1)) == 0 && q + d < 64 && r + d < len) s[p] = s[p] + s[p + d];
+            rr[e] = g - rs[lo];
+            ln[e] = rs[lo + 1] - rs[lo];
+        }
+    }
+    // canonical tree inside each 64-leaf unit
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = (int)threadIdx.x + e * B;
+            const int32_t r = rr[e], q = r & 63;
+            if (r >= 0 && (q & (2 * d - 1)) == 0 && q + d < 64 && r + d < ln[e])
+                s[p] = s[p] + s[p + d];
         }
         __syncthreads();
     }

@@ -112,8 +112,8 @@ def test_nontemporal_and_zmarch_shapes(env, orc):
         _check(out.cpu().numpy(), want)
 
 
-ZREG = [(64, 1, 1), (64, 2, 7), (64, 4, 64), (64, 8, 3), (128, 1, 2), (128, 2, 9), (128, 4, 5),
-        (128, 8, 64)]
+ZREG = [(64, 1, 1, 0), (64, 2, 7, 0), (64, 4, 64, 0), (64, 8, 3, 0), (128, 1, 2, 0), (128, 2, 9, 0),
+        (128, 4, 5, 0), (128, 8, 64, 0), (64, 1, 1, 2), (64, 4, 24, 3), (128, 2, 9, 2), (64, 8, 5, 2)]
 
 
 @pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 2),
@@ -128,11 +128,12 @@ def test_zreg_all_shapes(env, orc, shape, S):
     want = orc.jacobi7(u0_h, nx, ny, nz, S)
     u0 = torch.from_numpy(u0_h).to(dev)
     out = torch.empty_like(u0)
-    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, bx, by, bz, 0) for bx, by, bz in ZREG]
+    # flags: 1 streaming stores, 2 halo prefetch
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG, bx, by, bz, fl) for bx, by, bz, fl in ZREG]
     h = ao.region_declare_variants(f"gpu_zreg_{nx}_{ny}_{nz}", ao.AO_JACOBI7_F64, vs,
                                    model_type="roundrobin")
     a = ao.jacobi_args(u0, out, nx, ny, nz, S)
-    for v, (bx, by, bz) in enumerate(ZREG):
+    for v, (bx, by, bz, _) in enumerate(ZREG):
         out.fill_(-1.0)
         if bx == 128 and nx % 2:
             with pytest.raises(ao.AdaptError):
