@@ -114,6 +114,79 @@ def kernel_only(variant: int, launches: int = 3):
                       "copy_bytes_each": 16 * n ** 3}), flush=True)
 
 
+def batch_workload(steps: int, warmup: int):
+    """256 uneven FP64 Jacobi grids (each dim log-uniform in [8, 256], seed 3),
+    5 sweeps each: per-instance region runs vs one persistent launch per
+    sweep (eager) vs the captured graph, after autotuning the tile per
+    size bucket.  Prints one JSON line."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    shapes = synth.batch_shapes(256, 8, 256, seed=3)
+    S = 5
+    ins, bufs = [], []
+    for q, (nx, ny, nz) in enumerate(shapes):
+        u0 = synth.grid_u01_torch(int(nx), int(ny), int(nz), seed=3000 + q, device=dev)
+        out = torch.empty_like(u0)
+        bufs.append((u0, out))
+        ins.append(ao.jacobi_args(u0, out, int(nx), int(ny), int(nz), S))
+    total = sum(16.0 * int(nx) * int(ny) * int(nz) * S for nx, ny, nz in shapes)
+    points = int(sum(int(nx) * int(ny) * int(nz) for nx, ny, nz in shapes))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps * 1e-3, (time.perf_counter() - t0) / steps
+
+    region = ao.region_declare_variants("bench_batch_single", ao.AO_JACOBI7_F64,
+                                        ao.jacobi_variants_sweep()[:5], model_type="roundrobin")
+
+    def per_instance(v):
+        def fn():
+            for a in ins:
+                ao.region_run(region, a, stream=stream, variant=v)
+        return fn
+    single = {}
+    for v in range(5):
+        single[v] = timed(per_instance(v))
+    b = ao.batch_create(ins)
+    t_default_eager = timed(lambda: ao.batch_run(b, stream=stream, use_graph=False))
+    t0 = time.perf_counter()
+    chosen = ao.batch_autotune(b, stream=stream, warmup=1, reps=3)
+    tune_s = time.perf_counter() - t0
+    t_eager = timed(lambda: ao.batch_run(b, stream=stream, use_graph=False))
+    t_graph = timed(lambda: ao.batch_run(b, stream=stream, use_graph=True))
+    inst, items, tiles = ao.batch_info(b)
+    best_single = min(single, key=lambda v: single[v][0])
+    res = {"metric": "batched region GB/s (256 uneven grids x 5 sweeps, one graph launch)",
+           "value": round(total / t_graph[0] / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "256 FP64 Jacobi grids, dims log-uniform [8,256] (seed 3), 5 sweeps",
+                      "points": points, "algorithmic_bytes": total},
+           "pct_hbm_peak": round(100.0 * total / t_graph[0] / 1e9 / HBM_PEAK_GBS, 2),
+           "graph_ms": round(t_graph[0] * 1e3, 4), "graph_wall_ms": round(t_graph[1] * 1e3, 4),
+           "eager_persistent_ms": round(t_eager[0] * 1e3, 4),
+           "eager_persistent_default_tiles_ms": round(t_default_eager[0] * 1e3, 4),
+           "per_instance_ms": {str(v): round(single[v][0] * 1e3, 4) for v in single},
+           "per_instance_wall_ms": {str(v): round(single[v][1] * 1e3, 4) for v in single},
+           "speedup_graph_vs_best_per_instance": round(single[best_single][0] / t_graph[0], 3),
+           "autotune_seconds": round(tune_s, 3), "autotuned_candidates": chosen,
+           "bucket_instances": inst, "bucket_items": items, "bucket_tiles": tiles}
+    ao.batch_destroy(b)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,9 +195,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=None,
                     help="counter-collection mode: run one size-sweep variant at 512^3 only")
+    ap.add_argument("--workload", default="size-sweep", choices=["size-sweep", "batch"],
+                    help="size-sweep: the headline line; batch: the batched-launch line")
     args = ap.parse_args()
     if args.kernel_only is not None:
         kernel_only(args.kernel_only)
+        return
+    if args.workload == "batch":
+        batch_workload(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "

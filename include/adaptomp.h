@@ -127,9 +127,11 @@ typedef struct ao_region ao_region; /* opaque, library-owned */
  *   variants       num_variants entries (1..AO_MAX_VARIANTS), copied.
  *   min_train_data unique (features, variant) samples before training is
  *                  triggered; <= 0 means num_variants (Sec. 3.1 default).
- *   model_type     "mlp" (default, NULL), "exhaustive" (time every variant
- *                  for each new feature vector) or "roundrobin" (explore
- *                  only, never train).
+ *   model_type     "mlp" (default, NULL), "dtree" / "dtree,D" (the paper's
+ *                  decision-tree classifier of depth 2 / D on fastest-variant
+ *                  labels, trained and evaluated on the host), "exhaustive"
+ *                  (time every variant for each new feature vector) or
+ *                  "roundrobin" (explore only, never train).
  *   out            receives the handle. */
 int region_declare_variants(const char* model_name, int kind, const ao_variant* variants,
                             int num_variants, int min_train_data, const char* model_type,
@@ -187,7 +189,9 @@ typedef struct ao_train_opts {
 } ao_train_opts;
 
 /* Train the cost model on the profile database (Table 1
- * __apollo_region_train).  The dataset merges duplicate (features, variant)
+ * __apollo_region_train).  For a "dtree" region: CART with Gini impurity on
+ * one sample per distinct feature tuple labelled with its fastest variant;
+ * opts are ignored and final_loss receives the training error rate.  The dataset merges duplicate (features, variant)
  * samples by median time; inputs are z-scored, the target is ln(seconds)
  * minus its mean, the loss is the masked MSE of the measured variant; the
  * FP32 MLP 6-64-64-12 (ReLU) is trained with Adam on the GPU by the

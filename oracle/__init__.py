@@ -17,7 +17,9 @@ Contents (paper section cited on each function):
   * the MLP cost model, FP64, forward / backward / Adam (the learned
     selector that replaces the paper's depth-2 decision tree of Sec. 3.1
     ``model_type`` and Sec. 4; every detail of it is a reading, see
-    ``mlp_*``).
+    ``mlp_*``);
+  * the paper's own model, a CART decision-tree classifier on
+    fastest-variant labels (``dtree_*``).
 """
 from __future__ import annotations
 
@@ -389,5 +391,92 @@ def mlp_select(theta, ds_or_norm: dict, features, num_variants: int) -> int:
     best = 0
     for k in range(1, num_variants):
         if o[k] < o[best]:
+            best = k
+    return best
+
+
+# --------------------------------------------------------------------------
+# Decision-tree classifier (Sec. 3.1 model_type dtree; depth 2 in Sec. 4),
+# the paper's own model: CART grown by minimising the weighted Gini impurity
+# sum_child (n_child / n) * (1 - sum_k p_k^2), evaluated exactly with
+# rationals; candidate thresholds halfway between consecutive distinct
+# values (computed in double from the float32 features); ties to the lower
+# feature index, then the lower threshold; growth stops at the depth limit
+# or on a pure node.  Labels: fastest variant per feature tuple (Sec. 2).
+# --------------------------------------------------------------------------
+
+def label_records(records, num_variants: int):
+    """(features, variant, seconds) records -> (feature tuples, labels): per
+    distinct float32 feature tuple, in order of first appearance, the
+    variant with the lowest median time (ties to the lowest id)."""
+    groups = OrderedDict()
+    for feats, var, sec in records:
+        key = tuple(float(v) for v in np.asarray(feats, dtype=np.float32).tolist())
+        groups.setdefault(key, [[] for _ in range(num_variants)])[int(var)].append(float(sec))
+    X, y = [], []
+    for key, per in groups.items():
+        med = [float(np.median(t)) if t else math.inf for t in per]
+        best = 0
+        for v in range(1, num_variants):
+            if med[v] < med[best]:
+                best = v
+        X.append(list(key))
+        y.append(best)
+    return X, y
+
+
+def _gini_weighted(groups, num_classes):
+    from fractions import Fraction
+    n = sum(len(g) for g in groups)
+    total = Fraction(0)
+    for g in groups:
+        if not g:
+            continue
+        imp = Fraction(1) - sum(Fraction(sum(1 for c in g if c == k), len(g)) ** 2
+                                for k in range(num_classes))
+        total += Fraction(len(g), n) * imp
+    return total
+
+
+def dtree_fit(X, y, depth: int, num_classes: int) -> dict:
+    """Grow the tree; nodes are dicts {feature (-1 = leaf), threshold, left,
+    right, counts}."""
+    X = [[float(np.float32(v)) for v in row] + [0.0] * (N_IN - len(row)) for row in X]
+
+    def build(idx, d):
+        counts = [sum(1 for i in idx if y[i] == k) for k in range(num_classes)]
+        node = {"feature": -1, "threshold": 0.0, "left": None, "right": None, "counts": counts}
+        if d >= depth or sum(1 for c in counts if c > 0) <= 1 or len(idx) < 2:
+            return node
+        best = None
+        for f in range(N_IN):
+            vals = sorted(set(X[i][f] for i in idx))
+            for a, b in zip(vals, vals[1:]):
+                thr = 0.5 * (a + b)
+                left = [y[i] for i in idx if X[i][f] <= thr]
+                right = [y[i] for i in idx if X[i][f] > thr]
+                g = _gini_weighted([left, right], num_classes)
+                if best is None or g < best[0]:
+                    best = (g, f, thr)
+        if best is None:
+            return node
+        _, f, thr = best
+        node["feature"], node["threshold"] = f, thr
+        node["left"] = build([i for i in idx if X[i][f] <= thr], d + 1)
+        node["right"] = build([i for i in idx if X[i][f] > thr], d + 1)
+        return node
+
+    return build(list(range(len(X))), 0)
+
+
+def dtree_predict(tree: dict, features, allowed=None) -> int:
+    """Leaf majority among allowed classes (ties to the lowest id)."""
+    f = [float(np.float32(v)) for v in features] + [0.0] * (N_IN - len(features))
+    node = tree
+    while node["feature"] >= 0:
+        node = node["left"] if f[node["feature"]] <= node["threshold"] else node["right"]
+    best = -1
+    for k, c in enumerate(node["counts"]):
+        if (allowed is None or k in allowed) and c > 0 and (best < 0 or c > node["counts"][best]):
             best = k
     return best

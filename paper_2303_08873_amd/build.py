@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libadaptomp.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["jacobi.hip", "spmv.hip", "mlp.hip", "batch.hip", "runtime.cpp", "capi_mlp.cpp"]
+HIP_SOURCES = ["jacobi.hip", "spmv.hip", "mlp.hip", "batch.hip", "runtime.cpp", "capi_mlp.cpp",
+               "dtree.cpp"]
 HOST_SOURCES = ["host_jacobi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

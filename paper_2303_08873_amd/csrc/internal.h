@@ -81,6 +81,20 @@ hipError_t mlp_select_launch(const float* params, const MlpNorm* norm, const flo
                              int batch, int num_variants, int allowed_mask, int32_t* ids,
                              float* pred, hipStream_t s);
 
+// Decision-tree classifier (host).
+struct DTree {
+    struct Node {
+        int feature = -1;        // -1: leaf
+        double threshold = 0.0;  // f <= threshold goes left
+        int left = -1, right = -1;
+        std::vector<int> counts;  // class counts of the node's samples
+    };
+    std::vector<Node> nodes;
+    void train(const std::vector<std::vector<float>>& feats, const std::vector<int>& labels,
+               int max_depth, int num_classes);
+    int predict(const float* f, int allowed_mask) const;  // -1 if no allowed class
+};
+
 // Batched Jacobi.
 struct BatchItem {
     int32_t inst;        // instance index

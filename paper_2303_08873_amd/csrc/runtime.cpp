@@ -117,6 +117,8 @@ struct ao_region {
     double last_train_seconds = 0.0;
 
     // model
+    int dtree_depth = 0;  // > 0: model type "dtree[,depth]"
+    DTree tree;
     bool trained = false;
     std::vector<float> params;  // host copy
     MlpNorm norm{};
@@ -629,7 +631,8 @@ int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss);
 // count has doubled.
 void maybe_train(ao_region* r) {
     const int64_t nu = (int64_t)r->uniq.size();
-    if (r->model_type == "mlp" && !r->trained && nu >= r->min_train && nu >= r->retrain_at) {
+    const bool learns = r->model_type == "mlp" || r->dtree_depth > 0;
+    if (learns && !r->trained && nu >= r->min_train && nu >= r->retrain_at) {
         if (train_locked(r, nullptr, nullptr) < 0) {
             r->train_failures += 1;
             r->retrain_at = 2 * nu;
@@ -667,8 +670,57 @@ SpmvPlan::~SpmvPlan() {
 namespace ao {
 namespace {
 
+// Decision tree: one sample per distinct feature tuple, labelled with its
+// fastest variant (median per variant, ties to the lowest id).
+int train_dtree(ao_region* r, double* final_loss) {
+    const uint64_t t0 = now_ns();
+    std::unordered_map<FeatKey, std::vector<std::vector<double>>, FeatKeyHash> by;
+    std::vector<FeatKey> order;
+    std::unordered_map<FeatKey, const Record*, FeatKeyHash> first;
+    const int V = (int)r->variants.size();
+    for (const Record& rec : r->db) {
+        if (!std::isfinite(rec.seconds) || rec.seconds <= 0.0) continue;
+        const FeatKey k = make_key(rec.f);
+        auto it = by.find(k);
+        if (it == by.end()) {
+            it = by.emplace(k, std::vector<std::vector<double>>(V)).first;
+            order.push_back(k);
+            first[k] = &rec;
+        }
+        it->second[rec.variant].push_back(rec.seconds);
+    }
+    if (order.empty()) return fail(AO_ESTATE, "no usable profile records to train on");
+    std::vector<std::vector<float>> feats;
+    std::vector<int> labels;
+    for (const FeatKey& k : order) {
+        int best = -1;
+        double bt = INFINITY;
+        for (int v = 0; v < V; ++v) {
+            const double m = median_of(by[k][v]);
+            if (m < bt) {
+                bt = m;
+                best = v;
+            }
+        }
+        if (best < 0) continue;
+        feats.emplace_back(first[k]->f, first[k]->f + AO_MAX_FEATURES);
+        labels.push_back(best);
+    }
+    r->tree.train(feats, labels, r->dtree_depth, V);
+    int hits = 0;
+    for (size_t q = 0; q < feats.size(); ++q)
+        hits += r->tree.predict(feats[q].data(), (1 << V) - 1) == labels[q];
+    r->trained = true;
+    r->trainings += 1;
+    r->memo.clear();
+    r->last_train_seconds = (double)(now_ns() - t0) * 1e-9;
+    if (final_loss) *final_loss = 1.0 - (double)hits / (double)feats.size();  // training error
+    return AO_OK;
+}
+
 int train_locked(ao_region* r, const ao_train_opts* opts, double* final_loss) {
     harvest(r, true);
+    if (r->dtree_depth > 0) return train_dtree(r, final_loss);
     ao_train_opts o{200, 256, 1e-3f, 7};
     if (opts) o = *opts;
     if (o.epochs < 0 || o.batch <= 0 || !(o.lr > 0.0f))
@@ -918,8 +970,15 @@ int region_declare_variants(const char* model_name, int kind, const ao_variant* 
     if (!variants || num_variants < 1 || num_variants > AO_MAX_VARIANTS)
         return fail(AO_EINVAL, "need 1..12 variants");
     const std::string mt = model_type ? model_type : "mlp";
-    if (mt != "mlp" && mt != "exhaustive" && mt != "roundrobin")
-        return fail(AO_EINVAL, "model_type must be mlp, exhaustive or roundrobin");
+    int depth = 0;
+    if (mt == "dtree") {
+        depth = 2;  // the paper's default depth
+    } else if (mt.rfind("dtree,", 0) == 0) {
+        depth = atoi(mt.c_str() + 6);
+        if (depth < 1 || depth > 16) return fail(AO_EINVAL, "dtree depth must be 1..16");
+    } else if (mt != "mlp" && mt != "exhaustive" && mt != "roundrobin") {
+        return fail(AO_EINVAL, "model_type must be mlp, dtree[,depth], exhaustive or roundrobin");
+    }
     for (int i = 0; i < num_variants; ++i) {
         int rc = validate_variant(kind, variants[i], i);
         if (rc) return rc;
@@ -943,6 +1002,7 @@ int region_declare_variants(const char* model_name, int kind, const ao_variant* 
     r->variants.assign(variants, variants + num_variants);
     r->min_train = mtd;
     r->model_type = mt;
+    r->dtree_depth = depth;
     if (hipGetDevice(&r->device) != hipSuccess) {
         (void)hipGetLastError();
         r->device = -1;
@@ -980,6 +1040,21 @@ int region_run(ao_region* r, const ao_args* a, const float* features, void* stre
             } else {
                 rc = exhaustive_choice(r, a, f, s, 1, 3, &vid);
                 if (rc) return rc;
+                r->memo[key] = vid;
+            }
+        } else if (r->dtree_depth > 0 && r->trained) {
+            auto it = r->memo.find(key);
+            if (it != r->memo.end() && !(r->failed_mask & (1 << it->second))) {
+                vid = it->second;
+            } else {
+                const int V = (int)r->variants.size();
+                vid = r->tree.predict(f, ((1 << V) - 1) & ~r->failed_mask);
+                if (vid < 0) {
+                    rc = exhaustive_choice(r, a, f, s, 0, 1, &vid);
+                    if (rc) return rc;
+                    r->fallbacks += 1;
+                    status = AO_NOTE_FALLBACK;
+                }
                 r->memo[key] = vid;
             }
         } else if (r->model_type == "mlp" && r->trained) {
@@ -1080,7 +1155,16 @@ int selector_select(ao_region* r, const float* features, int batch, int* variant
         return fail(AO_EINVAL, "bad batch / buffers");
     std::lock_guard<std::mutex> g(r->mu);
     if (batch == 0) return AO_OK;
-    if (r->trained) {
+    if (r->trained && r->dtree_depth > 0) {
+        const int V = (int)r->variants.size();
+        const int allowed = ((1 << V) - 1) & ~r->failed_mask;
+        bool ok = true;
+        for (int b = 0; b < batch; ++b) {
+            variants_out[b] = r->tree.predict(features + (size_t)b * AO_MAX_FEATURES, allowed);
+            ok = ok && variants_out[b] >= 0;
+        }
+        if (ok) return AO_OK;
+    } else if (r->trained) {
         int rc = infer(r, features, batch, variants_out);
         if (rc <= 0) return rc;
     }
@@ -1149,8 +1233,9 @@ int region_save(ao_region* r, const char* path) {
         w.put<double>(rec.seconds);
         w.put<uint64_t>(rec.t_ns);
     }
-    w.put<uint32_t>(r->trained ? 1u : 0u);
-    if (r->trained) {
+    const bool mlp_model = r->trained && r->dtree_depth == 0;
+    w.put<uint32_t>(mlp_model ? 1u : 0u);
+    if (mlp_model) {
         w.put(r->params.data(), AO_MLP_PARAMS * 4);
         w.put(r->norm);
         w.put(r->fmin, sizeof(r->fmin));
@@ -1242,7 +1327,8 @@ int region_load(ao_region* r, const char* path) {
     r->uniq.clear();
     for (const Record& rec : r->db) r->uniq.insert(UKey{make_key(rec.f), rec.variant});
     r->memo.clear();
-    r->trained = has_model != 0;
+    r->trained = has_model != 0 && r->dtree_depth == 0;
+    if (r->dtree_depth > 0) r->tree.nodes.clear();  // a tree is rebuilt by selector_train
     if (has_model) {
         r->params = params;
         r->norm = norm;

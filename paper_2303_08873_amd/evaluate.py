@@ -125,8 +125,33 @@ def run(n_train=2000, n_test=2000, train_seed=4, test_seed=40, max_dim=512, warm
     lat = np.array(lat)
     exh_cost = table.sum(axis=1)[:lat.size]
 
+    # the paper's model: depth-2 decision tree on the same records
+    import os
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "records.bin")
+        ao.region_save(region, path)
+        dt = ao.region_declare_variants(f"eval_dt_{train_seed}_{n_train}", ao.AO_JACOBI7_F64,
+                                        jacobi_variants_sweep(), min_train_data=10 ** 9,
+                                        model_type="dtree")
+        ao.region_load(dt, path)
+    t0 = time.perf_counter()
+    dt_err = ao.selector_train(dt)
+    dt_train_s = time.perf_counter() - t0
+    _, ids_dt = ao.selector_select(dt, feats)
+    ids_dt = np.array(ids_dt)
+    lat_dt = []
+    for f in feats[:min(n_test, 500)]:
+        t1 = time.perf_counter()
+        ao.selector_select(dt, [f])
+        lat_dt.append(time.perf_counter() - t1)
+    ao.region_destroy(dt)
+
     idx = np.arange(n_test)
     result.update({
+        "dtree_depth2": _stats(table[idx, ids_dt], t_best),
+        "dtree_train_error": dt_err, "dtree_train_seconds": dt_train_s,
+        "dtree_selection_latency_us_median": float(np.median(lat_dt) * 1e6),
         "train_final_loss": loss, "train_seconds": train_wall,
         "train_kernel_seconds": ao.region_stats(region).last_train_seconds,
         "learned": _stats(table[idx, ids], t_best),
