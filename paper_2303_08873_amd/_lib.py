@@ -62,6 +62,14 @@ class Stats(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one.  Loading torch first makes this library bind to that runtime, so
+    # the process holds a single HIP runtime whose device pointers and
+    # streams both sides share.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(lib_path):
         raise ImportError(f"{lib_path} is not built; run `python paper_2303_08873_amd/build.py` "
                           "(the package has no fallback path)")
