@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -187,6 +189,111 @@ def batch_workload(steps: int, warmup: int):
     print(json.dumps(res), flush=True)
 
 
+def spmv_workload(steps: int, warmup: int):
+    """FP64 CSR SpMV region, n = 2^22 rows, Pareto-tail rows (index 1.5, mean
+    16, max 4096), seed 5; 9 variants {thread-row, wave-row, merge-path} x
+    {64, 256, 1024}.  The cost model is trained on profiled matrices of other
+    sizes and row-length laws (n 2^14..2^22, tail 1.2/1.5/2/3, mean 4/16/64,
+    seeds 50+), then chooses on held-out matrices (2^21 and the 2^22 target);
+    regret against their exhaustive tables.  Prints one JSON line."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    V = 9
+    region = ao.region_declare_variants("bench_spmv", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
+                                        min_train_data=10 ** 9, model_type="mlp")
+
+    def load(n, seed, tail=1.5, mean=16.0):
+        m = synth.csr_matrix(n, seed, mean=mean, tail=tail, max_len=4096)
+        t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        nnz = int(m["col"].size)
+        return t, y, ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz), nnz
+
+    t0 = time.perf_counter()
+    seed = 50
+    for lg in (14, 16, 18, 20, 22):
+        for tail in (1.2, 1.5, 2.0, 3.0):
+            for mean in (4.0, 16.0, 64.0):
+                t, y, a, _ = load(1 << lg, seed, tail, mean)
+                ao.region_profile(region, a, warmup=1, reps=3, stream=stream, record=True,
+                                  num_variants=V)
+                seed += 1
+                del t, y
+    train_s = time.perf_counter() - t0
+    loss = ao.selector_train(region, epochs=400, batch=64, lr=3e-3, seed=7)
+    _log(f"spmv selector: {seed - 50} training matrices in {train_s:.0f} s, loss {loss:.4g}")
+
+    held = [(1 << 21, 500 + q, tail, mean) for q, (tail, mean) in
+            enumerate([(1.2, 16.0), (1.5, 4.0), (2.0, 64.0), (3.0, 16.0), (1.5, 32.0), (2.5, 8.0)])]
+    held.append((1 << 22, 5, 1.5, 16.0))
+    regrets, rows = [], []
+    for n, sd, tail, mean in held:
+        t, y, a, nnz = load(n, sd, tail, mean)
+        med = ao.region_profile(region, a, warmup=1, reps=5, stream=stream, num_variants=V)
+        _, ids = ao.selector_select(region, [ao.region_features(region, a, stream=stream)])
+        chosen = ids[0]
+        best = min(range(V), key=lambda v: med[v])
+        regrets.append(med[chosen] / med[best] - 1.0)
+        byt = 12 * nnz + 4 * (n + 1) + 16 * n
+        rows.append({"n": n, "seed": sd, "tail": tail, "mean": mean, "nnz": nnz,
+                     "chosen": chosen, "best": best, "regret_pct": round(100 * regrets[-1], 3),
+                     "gbs": [round(byt / x / 1e9, 1) for x in med]})
+        if n == 1 << 22:
+            target = (t, y, a, nnz, chosen, med, byt)
+        else:
+            del t, y
+    t, y, a, nnz, chosen, med, byt = target
+    for _ in range(warmup):
+        ao.region_run(region, a, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ao.region_run(region, a, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / steps * 1e-3
+    r = np.asarray(regrets) + 1.0
+    res = {"metric": "SpMV region GB/s (learned selection); selector regret %",
+           "value": round(byt / sec / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "CSR SpMV n=2^22, Pareto rows tail 1.5 mean 16 max 4096, seed 5",
+                      "nnz": nnz, "algorithmic_bytes": byt},
+           "pct_hbm_peak": round(100.0 * byt / sec / 1e9 / HBM_PEAK_GBS, 2),
+           "chosen_variant": chosen, "us_per_spmv": round(sec * 1e6, 2),
+           "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
+           "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
+           "held_out": rows}
+    print(json.dumps(res), flush=True)
+
+
+def spmv_kernel_only(variant: int, launches: int = 5):
+    """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
+    executions."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = 1 << 22
+    m = synth.csr_matrix(n, 5)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    region = ao.region_declare_variants("bench_spmv_kernel_only", ao.AO_CSR_SPMV_F64,
+                                        ao.spmv_variants(), model_type="roundrobin")
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+    for _ in range(launches):
+        ao.region_run(region, a, stream=stream, variant=variant)
+    torch.cuda.synchronize()
+    print(json.dumps({"spmv_kernel_only": variant, "launches": launches,
+                      "nnz": int(m["col"].size)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,14 +302,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=None,
                     help="counter-collection mode: run one size-sweep variant at 512^3 only")
-    ap.add_argument("--workload", default="size-sweep", choices=["size-sweep", "batch"],
-                    help="size-sweep: the headline line; batch: the batched-launch line")
+    ap.add_argument("--workload", default="size-sweep", choices=["size-sweep", "batch", "spmv"],
+                    help="size-sweep: the headline line; batch / spmv: the other region lines")
     args = ap.parse_args()
     if args.kernel_only is not None:
-        kernel_only(args.kernel_only)
+        if args.workload == "spmv":
+            spmv_kernel_only(args.kernel_only)
+        else:
+            kernel_only(args.kernel_only)
         return
     if args.workload == "batch":
         batch_workload(args.steps, args.warmup)
+        return
+    if args.workload == "spmv":
+        spmv_workload(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "

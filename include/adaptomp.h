@@ -113,6 +113,13 @@ typedef struct ao_args {
     double* y;
     int32_t n;
     int64_t nnz;
+    /* Identity of the sparsity structure (the contents of row_ptr): the
+     * per-matrix plan (features, merge-path partition) is cached under
+     * (structure_id, row_ptr, n, nnz).  The caller gives a matrix a new id
+     * whenever row_ptr may hold a different structure (a freed and reused
+     * buffer, an edited matrix).  0 = unknown: the plan is rebuilt on every
+     * call. */
+    uint64_t structure_id;
 } ao_args;
 
 typedef struct ao_region ao_region; /* opaque, library-owned */
@@ -168,6 +175,12 @@ int region_run(ao_region* r, const ao_args* a, const float* features, void* stre
  * features and took `seconds`) -- Table 1 __apollo_region_end.  Appends to
  * the profile database and applies the same train trigger as region_run. */
 int region_record(ao_region* r, const float* features, int variant, double seconds);
+
+/* Compute the feature vector of one execution without running it (Table 1
+ * __apollo_region_set_feature values): features[AO_MAX_FEATURES] as listed
+ * for region_run.  SpMV features are computed on the GPU once per matrix
+ * (row_ptr, n, nnz) and cached; synchronises `stream` in that case. */
+int region_features(ao_region* r, const ao_args* a, void* stream, float* features);
 
 #define AO_PROFILE_RECORD 1 /* append the timed runs to the profile database */
 

@@ -3,6 +3,7 @@ same names, argument marshalling only."""
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,7 +45,8 @@ class Args(ctypes.Structure):
                 ("sweeps", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
-                ("n", ctypes.c_int32), ("nnz", ctypes.c_int64)]
+                ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("structure_id", ctypes.c_uint64)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -80,6 +82,7 @@ def _load():
         "region_declare_variants": [ctypes.c_char_p, I, P, I, I, ctypes.c_char_p, P],
         "region_run": [P, P, P, P, I, P],
         "region_record": [P, P, I, ctypes.c_double],
+        "region_features": [P, P, P, P],
         "region_profile": [P, P, P, I, I, I, P, I, P],
         "selector_train": [P, P, P],
         "selector_select": [P, P, I, P],
@@ -163,6 +166,12 @@ def region_run(region, args: Args, features=None, stream=None, variant: int = -1
     rc = _check(lib.region_run(region, ctypes.byref(args), fbuf, _stream(stream), variant,
                                ctypes.byref(chosen)))
     return rc, chosen.value
+
+
+def region_features(region, args: Args, stream=None) -> list:
+    out = (ctypes.c_float * AO_MAX_FEATURES)()
+    _check(lib.region_features(region, ctypes.byref(args), _stream(stream), out))
+    return list(out)
 
 
 def region_record(region, features, variant: int, seconds: float) -> None:
@@ -294,8 +303,15 @@ def jacobi_args(u0, out, nx: int, ny: int, nz: int, sweeps: int, resident: int =
     return a
 
 
-def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int) -> Args:
+_structure_ids = itertools.count(1)
+
+
+def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int, structure_id: int | None = None) -> Args:
+    """Arguments of one SpMV execution.  Unless given, every call issues a
+    fresh structure id, so the library's per-matrix plan is shared by the
+    executions that reuse this Args object and never by another matrix."""
     a = Args()
+    a.structure_id = next(_structure_ids) if structure_id is None else structure_id
     a.kind = AO_CSR_SPMV_F64
     a.resident = 1
     a.row_ptr, a.col, a.val, a.x, a.y = _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y)

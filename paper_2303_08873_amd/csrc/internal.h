@@ -30,6 +30,7 @@ void jacobi_host_sweeps(const ao_variant& v, const double* u0, double* out, doub
 
 // SpMV: per-matrix plan (features, merge-path partition) built on the GPU.
 struct SpmvPlan {
+    uint64_t structure_id = 0;
     const int32_t* row_ptr = nullptr;
     int32_t n = 0;
     int64_t nnz = 0;

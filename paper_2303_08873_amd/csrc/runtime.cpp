@@ -292,10 +292,21 @@ void harvest(ao_region* r, bool block) {
 }
 
 SpmvPlan* get_plan(ao_region* r, const ao_args* a, hipStream_t s, int* rc) {
-    for (auto& p : r->plans)
-        if (p->row_ptr == a->row_ptr && p->n == a->n && p->nnz == a->nnz) return p.get();
+    if (a->structure_id != 0) {
+        for (auto& p : r->plans)
+            if (p->structure_id == a->structure_id && p->row_ptr == a->row_ptr &&
+                p->n == a->n && p->nnz == a->nnz)
+                return p.get();
+    }
+    // drop plans whose id is unknown or now names other buffers; keep <= 8
+    for (auto it = r->plans.begin(); it != r->plans.end();) {
+        const bool stale = (*it)->structure_id == 0 ||
+                           ((*it)->structure_id == a->structure_id);
+        it = stale ? r->plans.erase(it) : it + 1;
+    }
     if (r->plans.size() >= 8) r->plans.erase(r->plans.begin());
     auto p = std::make_unique<SpmvPlan>();
+    p->structure_id = a->structure_id;
     p->row_ptr = a->row_ptr;
     p->n = a->n;
     p->nnz = a->nnz;
@@ -1096,6 +1107,14 @@ int region_run(ao_region* r, const ao_args* a, const float* features, void* stre
     if (chosen) *chosen = vid;
     maybe_train(r);
     return status;
+}
+
+int region_features(ao_region* r, const ao_args* a, void* stream, float* features) {
+    if (!r || !features) return fail(AO_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(r->mu);
+    int rc = validate_args(r, a);
+    if (rc) return rc;
+    return compute_features(r, a, (hipStream_t)stream, features);
 }
 
 int region_record(ao_region* r, const float* features, int variant, double seconds) {

@@ -348,6 +348,9 @@ __global__ void k_partition(int n, int nb, int D, const int32_t* __restrict__ ro
     sunit[b] = j;
 }
 
+// The partition tables must describe this row_ptr (the runtime keys them on
+// the structure id); every index below is nevertheless clamped to its
+// buffer, so tables of another matrix give wrong sums, never stray accesses.
 template <int B>
 __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col,
@@ -357,20 +360,22 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
                                                   const int32_t* __restrict__ srow,
                                                   const int32_t* __restrict__ sunit,
                                                   const int32_t* __restrict__ unit_ptr,
-                                                  double* __restrict__ unit_sums) {
+                                                  double* __restrict__ unit_sums, int64_t units) {
     constexpr int D = 4 * B;
     // a unit that starts just below the block's cost limit may extend 64
     // leaves past it: at most D + 64 leaves and D rows per block
     __shared__ double s[D + 64];
     __shared__ int32_t rs[D + 2];  // row starts (global nnz offsets) of the block's rows
     const int b = (int)blockIdx.x;
-    const int i0 = srow[b], j0 = sunit[b], i1 = srow[b + 1], j1 = sunit[b + 1];
-    const int32_t e0 = (i0 < n ? row_ptr[i0] : row_ptr[n]) + 64 * j0;
-    int32_t e1 = (i1 < n ? row_ptr[i1] : row_ptr[n]) + 64 * j1;
+    const int i0 = min(max(srow[b], 0), n), i1 = min(max(srow[b + 1], 0), n);
+    const int j0 = max(sunit[b], 0), j1 = max(sunit[b + 1], 0);
+    const int32_t kbeg = row_ptr[0], kend = row_ptr[n];
+    const int32_t e0 = (i0 < n ? row_ptr[i0] : kend) + 64 * j0;
+    int32_t e1 = (i1 < n ? row_ptr[i1] : kend) + 64 * j1;
     if (i1 < n) e1 = min(e1, row_ptr[i1 + 1]);
-    const int cnt = e1 - e0;                     // <= D + 64
-    const int ilast = (j1 > 0) ? i1 : i1 - 1;    // last row touched
-    const int nrows = ilast - i0 + 1;            // <= D
+    const int cnt = min(max(e1 - e0, 0), D + 64);
+    const int ilast = (j1 > 0) ? i1 : i1 - 1;  // last row touched
+    const int nrows = min(max(ilast - i0 + 1, 0), min(D, n - i0));
     for (int t = (int)threadIdx.x; t <= nrows && t < D + 2; t += B) rs[t] = row_ptr[i0 + t];
     constexpr int E = 4 + (64 + B - 1) / B;  // leaves per thread: ceil((D + 64) / B)
 #pragma unroll
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
         const int p = (int)threadIdx.x + e * B;
         if (p < cnt) {
             const int64_t k = (int64_t)e0 + p;
-            s[p] = val[k] * x[col[k]];
+            s[p] = (k >= kbeg && k < kend) ? val[k] * x[col[k]] : 0.0;
         }
     }
     __syncthreads();
@@ -407,49 +412,58 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
         for (int e = 0; e < E; ++e) {
             const int p = (int)threadIdx.x + e * B;
             const int32_t r = rr[e], q = r & 63;
-            if (r >= 0 && (q & (2 * d - 1)) == 0 && q + d < 64 && r + d < ln[e])
+            if (r >= 0 && (q & (2 * d - 1)) == 0 && q + d < 64 && r + d < ln[e] && p + d < cnt)
                 s[p] = s[p] + s[p + d];
         }
         __syncthreads();
     }
     // rows: complete ones are finished here, split ones leave their unit sums
+    constexpr int kMaxUnits = (D + 64) / 64 + 1;  // units of one row inside one block
     for (int t = (int)threadIdx.x; t < nrows; t += B) {
         const int i = i0 + t;
         const int32_t rb = rs[t], re = rs[t + 1];
         const int32_t nu = re > rb ? (re - rb + 63) / 64 : 1;
         const int32_t ja = (t == 0) ? j0 : 0;
-        const int32_t jb = (i == i1) ? j1 : nu;  // units [ja, jb) are in this block
+        const int32_t jb = min((i == i1) ? j1 : nu, ja + kMaxUnits);  // units [ja, jb) here
         const bool whole = (ja == 0) && (i < i1);
         if (whole) {
             Counter c;
             for (int32_t j = ja; j < jb; ++j) {
                 const int32_t g = rb + 64 * j;
-                if (g < re) c.push(s[g - e0]);
+                const int32_t o = g - e0;
+                if (g < re && o >= 0 && o < cnt) c.push(s[o]);
             }
             y[i] = c.finish();
         } else {
             for (int32_t j = ja; j < jb; ++j) {
                 const int32_t g = rb + 64 * j;
-                unit_sums[unit_ptr[i] + j] = (g < re) ? s[g - e0] : 0.0;
+                const int32_t o = g - e0;
+                const int64_t u = (int64_t)unit_ptr[i] + j;
+                if (u >= 0 && u < units) unit_sums[u] = (g < re && o >= 0 && o < cnt) ? s[o] : 0.0;
             }
         }
     }
 }
 
 // one thread per block boundary: the first boundary inside a row finishes it
-__global__ void k_merge_fixup(int nb, const int32_t* __restrict__ row_ptr,
+__global__ void k_merge_fixup(int n, int nb, const int32_t* __restrict__ row_ptr,
                               const int32_t* __restrict__ srow, const int32_t* __restrict__ sunit,
                               const int32_t* __restrict__ unit_ptr,
-                              const double* __restrict__ unit_sums, double* __restrict__ y) {
+                              const double* __restrict__ unit_sums, int64_t units,
+                              double* __restrict__ y) {
     const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (b <= 0 || b >= nb) return;
     if (sunit[b] == 0) return;
     const int i = srow[b];
+    if (i < 0 || i >= n) return;
     if (srow[b - 1] == i && sunit[b - 1] > 0) return;  // an earlier boundary splits this row
     Counter c;
     const int32_t len = row_ptr[i + 1] - row_ptr[i];
     const int32_t nu = (len + 63) / 64;
-    for (int32_t j = 0; j < nu; ++j) c.push(unit_sums[unit_ptr[i] + j]);
+    for (int32_t j = 0; j < nu; ++j) {
+        const int64_t u = (int64_t)unit_ptr[i] + j;
+        c.push((u >= 0 && u < units) ? unit_sums[u] : 0.0);
+    }
     y[i] = c.finish();
 }
 
@@ -516,7 +530,8 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
 #define AO_MP(BB)                                                                           \
     case BB:                                                                                \
         hipLaunchKernelGGL(k_merge_path<BB>, dim3(m->blocks), dim3(BB), 0, s, p.n, p.row_ptr, \
-                           col, val, x, y, m->srow, m->sunit, p.unit_ptr, p.unit_sums);     \
+                           col, val, x, y, m->srow, m->sunit, p.unit_ptr, p.unit_sums,      \
+                           p.units);                                                        \
         break;
         AO_MP(64) AO_MP(128) AO_MP(256) AO_MP(512) AO_MP(1024)
 #undef AO_MP
@@ -525,8 +540,9 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_fixup, dim3((m->blocks + 255) / 256), dim3(256), 0, s, m->blocks,
-                       p.row_ptr, m->srow, m->sunit, p.unit_ptr, p.unit_sums, y);
+    hipLaunchKernelGGL(k_merge_fixup, dim3((m->blocks + 255) / 256), dim3(256), 0, s, p.n,
+                       m->blocks, p.row_ptr, m->srow, m->sunit, p.unit_ptr, p.unit_sums, p.units,
+                       y);
     return hipGetLastError();
 }
 

@@ -150,3 +150,29 @@ def test_full_size_2_22(env, orc):
         got = y.cpu().numpy()
         assert np.array_equal(got, want), f"variant {v}: {int(np.sum(got != want))} rows differ"
     ao.region_destroy(h)
+
+
+def test_reused_buffers_same_n_and_nnz(env, orc):
+    # Regression: two matrices with equal n and nnz placed one after the other
+    # in the same device buffers must not share the per-matrix plan (each
+    # spmv_args call carries a fresh structure id).
+    ao, torch, dev, st = env
+    n = 1 << 14
+    ma = synth.csr_matrix(n, 54, mean=16.0, tail=1.5)
+    mb = synth.csr_matrix(n, 57, mean=16.0, tail=2.0)
+    assert ma["col"].size == mb["col"].size and not np.array_equal(ma["row_ptr"], mb["row_ptr"])
+    t = {k: torch.from_numpy(v).to(dev) for k, v in ma.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    h = ao.region_declare_variants("reuse", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
+                                   model_type="roundrobin")
+    for m in (ma, mb):
+        for k, v in m.items():
+            t[k].copy_(torch.from_numpy(v))
+        a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+        want = orc.spmv_canonical(m["row_ptr"], m["col"], m["val"], m["x"])
+        for v in range(9):
+            y.fill_(float("nan"))
+            ao.region_run(h, a, stream=st, variant=v)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy(), want), v
+    ao.region_destroy(h)
