@@ -30,7 +30,7 @@ constexpr double kC = 0x1.5555555555555p-3;  // fl(1/6)
 constexpr int kThreads = 256;
 constexpr int kBuckets = 5;
 
-enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2 };
+enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2, kZreg4 = 4 };
 struct TileCfg {
     int kind, tx, ty, tz;
 };
@@ -39,6 +39,7 @@ constexpr TileCfg kCands[] = {
     {kDirect, 8, 8, 4},  {kDirect, 16, 16, 1}, {kDirect, 16, 8, 2},  {kDirect, 32, 8, 1},
     {kDirect, 64, 4, 1}, {kDirect, 16, 16, 4}, {kDirect, 8, 8, 16},  {kZreg1, 64, 4, 16},
     {kZreg2, 64, 8, 32}, {kZreg2, 64, 8, 64},  {kZreg1, 64, 4, 64},  {kZreg2, 64, 8, 16},
+    {kZreg4, 64, 16, 24}, {kZreg4, 64, 16, 32}, {kZreg4, 64, 16, 64}, {kZreg2, 64, 8, 24},
 };
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 // default candidate per bucket before autotuning
@@ -144,10 +145,21 @@ __device__ void tile_zreg(const Inst& in, const double* __restrict__ src, double
     }
 }
 
+// Items are dealt in windows of gridDim.x; inside a window the workgroup ->
+// item map is XCD-aware (workgroups go to the 8 XCDs round-robin), so each
+// XCD takes a contiguous run of neighbouring tiles and their halos meet in
+// its L2.
+__device__ __forceinline__ int xcd_slot(int b, int g) {
+    const int xcd = b % 8, local = b / 8, per = g / 8, rem = g % 8;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
 __global__ __launch_bounds__(kThreads) void k_batch_sweep(const Inst* __restrict__ insts,
                                                           const Item* __restrict__ items,
                                                           int nitems, int sweep) {
-    for (int w = (int)blockIdx.x; w < nitems; w += (int)gridDim.x) {
+    const int g = (int)gridDim.x;
+    const int slot = xcd_slot((int)blockIdx.x, g);
+    for (int w = slot; w < nitems; w += g) {
         const Item it = items[w];
         const Inst in = insts[it.inst];
         if (sweep >= in.sweeps) continue;
@@ -158,8 +170,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_sweep(const Inst* __restrict
             tile_direct(in, src, dst, it, c);
         else if (c.kind == kZreg1)
             tile_zreg<1>(in, src, dst, it, c);
-        else
+        else if (c.kind == kZreg2)
             tile_zreg<2>(in, src, dst, it, c);
+        else
+            tile_zreg<4>(in, src, dst, it, c);
     }
 }
 
