@@ -25,6 +25,10 @@
 //          A block is 4 such waves stacked in y (tile 64*VX x 4R).  With the
 //          halo-prefetch flag the halo of plane k+1 is also loaded during
 //          plane k, so no iteration waits on its own loads.
+//  zreg_t2 the register z-march with two sweeps fused per pass (temporal
+//          blocking): half the HBM traffic per sweep; strips of 64 lanes
+//          overlap by one point per side so the intermediate sweep's
+//          x-neighbours stay inside the wave (62 outputs per strip).
 //
 // All map blockIdx.x to tiles XCD-aware: the hardware deals workgroups to
 // the 8 XCDs round-robin, so consecutive logical tiles (which share z- and
@@ -255,6 +259,142 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
     }
 }
 
+// Two sweeps per pass (temporal blocking factor 2).  A wave owns 64 lanes
+// of x starting at i0 = 62*bi - 1 and R output rows; it keeps the input u on
+// rows j0-2 .. j0+R+1 for planes k-1, k, k+1 and the first-sweep values v on
+// rows j0-1 .. j0+R for planes k-2, k-1, k, all in registers.  In iteration
+// k it loads u(k+1), computes v(k) on all 64 lanes (strip edges from lanes 0
+// and 63's extra loads), then w(k-1) = J(v) on lanes 1..62.  v at positions
+// outside the grid is forced to +0.0 -- the ghost value a separate second
+// sweep would read -- so w is bit-identical to two sweeps.
+template <int R, bool NT>
+__device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
+                                             double* __restrict__ dst, int nx, int ny, int nz,
+                                             int nbx, int nby, int bz, unsigned nblocks) {
+    constexpr int RU = R + 4, RV = R + 2;
+    const unsigned b = xcd_remap(blockIdx.x, nblocks);
+    const int bi = (int)(b % (unsigned)nbx);
+    const unsigned t = b / (unsigned)nbx;
+    const int bj = (int)(t % (unsigned)nby);
+    const int kb = (int)(t / (unsigned)nby);
+    const int lane = (int)(threadIdx.x & 63);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int i0 = 62 * bi - 1;
+    const int i = i0 + lane;
+    const int j0 = (bj * kZregWaves + wave) * R;
+    if (j0 >= ny) return;  // wave-uniform
+    const int k0 = kb * bz;
+    const int k1 = min(nz, k0 + bz);
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const bool xin = i >= 0 && i < nx;
+    const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
+    const bool eok = (lane == 0 || lane == 63) && ie >= 0 && ie < nx;
+    auto ld = [&](int k, int j, int x, bool ok) -> double {
+        return (ok && k >= 0 && k < nz && j >= 0 && j < ny) ? src[(size_t)k * plane + (size_t)j * nx + x]
+                                                          : 0.0;
+    };
+    // registers hold only the rows each plane is read at:
+    //   um[q] = u(k-1) on rows j0-1+q   (centre rows of v)
+    //   uc[q], up[q] = u(k), u(k+1) on rows j0-2+q
+    //   vm[r] = v(k-2) on rows j0+r     (centre rows of w)
+    //   vc[q], vn[q] = v(k-1), v(k) on rows j0-1+q
+    double um[RV], uc[RU], up[RU];
+    double vm[R], vc[RV], vn[RV];
+#pragma unroll
+    for (int q = 0; q < RV; ++q) um[q] = ld(k0 - 2, j0 - 1 + q, i, xin);
+#pragma unroll
+    for (int q = 0; q < RU; ++q) uc[q] = ld(k0 - 1, j0 - 2 + q, i, xin);
+#pragma unroll
+    for (int r = 0; r < R; ++r) vm[r] = 0.0;  // v(k0-3) is never read
+#pragma unroll
+    for (int q = 0; q < RV; ++q) vc[q] = 0.0;  // v(k0-2) only feeds w(k0-1), never stored
+    for (int k = k0 - 1; k <= k1; ++k) {
+        double ex[RV];
+#pragma unroll
+        for (int q = 0; q < RU; ++q) up[q] = ld(k + 1, j0 - 2 + q, i, xin);
+#pragma unroll
+        for (int q = 0; q < RV; ++q) ex[q] = ld(k, j0 - 1 + q, ie, eok);
+        // v(k) on rows j0-1 .. j0+R, all lanes
+        const bool kin = k >= 0 && k < nz;
+#pragma unroll
+        for (int q = 0; q < RV; ++q) {
+            const int j = j0 - 1 + q;
+            const double c = uc[q + 1];
+            const double left = __shfl_up(c, 1), right = __shfl_down(c, 1);
+            const double xm = (lane == 0) ? ex[q] : left;
+            const double xp = (lane == 63) ? ex[q] : right;
+            double v = xm + xp;
+            v = v + uc[q];
+            v = v + uc[q + 2];
+            v = v + um[q];
+            v = v + up[q + 1];
+            vn[q] = (kin && xin && j >= 0 && j < ny) ? v * kC : 0.0;
+        }
+        // w(k-1) on rows j0 .. j0+R-1, lanes 1..62
+        const int kw = k - 1;
+        if (kw >= k0 && kw < k1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                const double c = vc[r + 1];
+                const double xm = __shfl_up(c, 1), xp = __shfl_down(c, 1);
+                double w = xm + xp;
+                w = w + vc[r];
+                w = w + vc[r + 2];
+                w = w + vm[r];
+                w = w + vn[r + 1];
+                if (lane >= 1 && lane <= 62 && xin && j < ny)
+                    store<NT>(dst + (size_t)kw * plane + (size_t)j * nx + i, w * kC);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RV; ++q) um[q] = uc[q + 1];
+#pragma unroll
+        for (int q = 0; q < RU; ++q) uc[q] = up[q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) vm[r] = vc[r + 1];
+#pragma unroll
+        for (int q = 0; q < RV; ++q) vc[q] = vn[q];
+    }
+}
+
+template <int R, bool NT>
+__global__ __launch_bounds__(64 * kZregWaves) void jac_zreg_t2(const double* __restrict__ src,
+                                                                double* __restrict__ dst, int nx,
+                                                                int ny, int nz, int nbx, int nby,
+                                                                int bz, unsigned nblocks) {
+    zreg_t2_body<R, NT>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+}
+
+// The same kernel compiled for at least 4 waves per SIMD (register budget
+// 128; the compiler may spill a little).
+template <int R, bool NT>
+__global__ __launch_bounds__(64 * kZregWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void jac_zreg_t2_occ(const double* __restrict__ src, double* __restrict__ dst, int nx, int ny,
+                     int nz, int nbx, int nby, int bz, unsigned nblocks) {
+    zreg_t2_body<R, NT>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+}
+
+template <int R>
+hipError_t launch_zreg_t2(bool nt, bool occ, dim3 grid, hipStream_t s, const double* src,
+                          double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
+                          unsigned nb) {
+    const dim3 block(64 * kZregWaves);
+    if (occ && nt)
+        hipLaunchKernelGGL((jac_zreg_t2_occ<R, true>), grid, block, 0, s, src, dst, nx, ny, nz,
+                           nbx, nby, bz, nb);
+    else if (occ)
+        hipLaunchKernelGGL((jac_zreg_t2_occ<R, false>), grid, block, 0, s, src, dst, nx, ny, nz,
+                           nbx, nby, bz, nb);
+    else if (nt)
+        hipLaunchKernelGGL((jac_zreg_t2<R, true>), grid, block, 0, s, src, dst, nx, ny, nz, nbx,
+                           nby, bz, nb);
+    else
+        hipLaunchKernelGGL((jac_zreg_t2<R, false>), grid, block, 0, s, src, dst, nx, ny, nz, nbx,
+                           nby, bz, nb);
+    return hipGetLastError();
+}
+
 template <int R, int VX>
 hipError_t launch_zreg(bool nt, bool pf, dim3 grid, hipStream_t s, const double* src, double* dst,
                        int nx, int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
@@ -356,6 +496,26 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
         return hipErrorInvalidConfiguration;
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, double* dst, int nx,
+                                  int ny, int nz, hipStream_t s) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+    const int R = v.by, bz = v.bz;
+    if (v.family != AO_FAM_JACOBI_ZREG_T2 || v.bx != 64 || bz <= 0)
+        return hipErrorInvalidConfiguration;
+    const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
+    const bool occ = (v.flags & AO_VF_OCCUPANCY) != 0;
+    const int nbx = cdiv(nx, 62), nby = cdiv(ny, kZregWaves * R);
+    const int64_t nb = (int64_t)nbx * nby * cdiv(nz, bz);
+    if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nb);
+    const unsigned u = (unsigned)nb;
+    if (R == 1) return launch_zreg_t2<1>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+    if (R == 2) return launch_zreg_t2<2>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+    if (R == 3) return launch_zreg_t2<3>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+    if (R == 4) return launch_zreg_t2<4>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+    return hipErrorInvalidConfiguration;
 }
 
 hipError_t hbm_copy(const double* src, double* dst, int64_t n, bool nt, hipStream_t s) {

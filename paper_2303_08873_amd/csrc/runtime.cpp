@@ -171,8 +171,11 @@ int validate_variant(int kind, const ao_variant& v, int id) {
         }
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "unknown target");
         if (v.family != AO_FAM_JACOBI_DIRECT && v.family != AO_FAM_JACOBI_ZMARCH &&
-            v.family != AO_FAM_JACOBI_ZREG)
+            v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2)
             return fail(AO_EINVAL, at + "unknown GPU Jacobi family");
+        if (v.family == AO_FAM_JACOBI_ZREG_T2 &&
+            (v.bx != 64 || v.by < 1 || v.by > 4 || v.bz <= 0))
+            return fail(AO_EINVAL, at + "two-sweep z-march needs bx 64, by 1..4, bz > 0");
         if (v.family == AO_FAM_JACOBI_ZREG &&
             ((v.bx != 64 && v.bx != 128) || (v.by != 1 && v.by != 2 && v.by != 4 && v.by != 8) ||
              v.bz <= 0))
@@ -369,6 +372,17 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
             if (rc) return rc;
             hipEvent_t e0 = get_event(r), e1 = get_event(r);
             if (!e0 || !e1) return fail(AO_EHIP, "event creation failed");
+            // launches: one per sweep, or (two-sweep family) one per pair plus
+            // a single register z-march sweep when S is odd
+            const bool pairs = v.family == AO_FAM_JACOBI_ZREG_T2;
+            const int L = pairs ? S / 2 + (S % 2) : S;
+            const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, v.by == 3 ? 2 : v.by,
+                                    v.bz, v.flags & AO_VF_NT_STORE};
+            auto launch = [&](int l, const double* src, double* dst) {
+                if (!pairs) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
+                if (l == 0 && (S % 2)) return jacobi_gpu_sweep(single, src, dst, nx, ny, nz, s);
+                return jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s);
+            };
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess && n > 0) {
                 if (a->resident) {
@@ -376,9 +390,9 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
                         e = hipMemcpyAsync(a->out, a->u0, n * 8, hipMemcpyDeviceToDevice, s);
                     } else {
                         const double* src = a->u0;
-                        for (int k = 0; k < S && e == hipSuccess; ++k) {
-                            double* dst = ((S - 1 - k) % 2 == 0) ? a->out : r->d_a;
-                            e = jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
+                        for (int k = 0; k < L && e == hipSuccess; ++k) {
+                            double* dst = ((L - 1 - k) % 2 == 0) ? a->out : r->d_a;
+                            e = launch(k, src, dst);
                             src = dst;
                         }
                     }
@@ -386,8 +400,8 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
                     e = hipMemcpyAsync(r->d_a, a->u0, n * 8, hipMemcpyHostToDevice, s);
                     double* p = r->d_a;
                     double* q = r->d_b;
-                    for (int k = 0; k < S && e == hipSuccess; ++k) {
-                        e = jacobi_gpu_sweep(v, p, q, nx, ny, nz, s);
+                    for (int k = 0; k < L && e == hipSuccess; ++k) {
+                        e = launch(k, p, q);
                         std::swap(p, q);
                     }
                     if (e == hipSuccess)

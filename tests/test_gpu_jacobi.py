@@ -144,6 +144,40 @@ def test_zreg_all_shapes(env, orc, shape, S):
         _check(out.cpu().numpy(), want)
 
 
+# (rows per wave, planes per block, flags: 1 streaming stores, 4 register cap)
+T2 = [(1, 1, 0), (1, 3, 1), (2, 16, 0), (2, 5, 1), (4, 64, 0), (4, 2, 1), (2, 100, 0), (1, 7, 0),
+      (3, 9, 0), (3, 4, 5), (4, 32, 5), (4, 7, 4)]
+
+
+@pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
+                                     ((257, 3, 4), 1), ((64, 32, 16), 2), ((6, 6, 6), 5),
+                                     ((63, 5, 7), 6), ((125, 18, 33), 8)])
+def test_two_sweep_family_all_shapes(env, orc, shape, S):
+    # temporal blocking: two sweeps fused per pass (plus one single sweep when
+    # S is odd), bit-identical to S separate sweeps
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=61 + nx + S)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG_T2, 64, r, bz, fl) for r, bz, fl in T2]
+    h = ao.region_declare_variants(f"gpu_t2_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                   model_type="roundrobin")
+    for resident in (1, 0):
+        if resident:
+            a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+        else:
+            uh = torch.from_numpy(u0_h).pin_memory()
+            oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
+            a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
+        for v in range(len(T2)):
+            (out if resident else oh).fill_(-1.0)
+            ao.region_run(h, a, stream=st, variant=v)
+            torch.cuda.synchronize()
+            _check((out if resident else oh).cpu().numpy(), want)
+
+
 def test_hbm_copy_probe(env):
     ao, torch, dev, st = env
     for n in (0, 1, 5, 4096, 1000003):
