@@ -79,8 +79,9 @@ enum ao_family {
     AO_FAM_JACOBI_ZREG = 3,   /* GPU: register z-march, strip bx (64|128) wide, by (1|2|4|8)
                                  rows per wave, 4 waves per block, bz planes per block */
     AO_FAM_JACOBI_ZREG_T2 = 4, /* GPU: register z-march with two sweeps fused per pass
-                                  (temporal blocking); bx = 64, by (1..4) rows per wave,
-                                  bz planes; an odd sweep count adds one single sweep */
+                                  (temporal blocking); bx = 64, by (1|2|3|4|6|8|10|12|16)
+                                  rows per wave, bz planes; an odd sweep count adds one
+                                  single sweep */
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
     AO_FAM_SPMV_MERGE_PATH = 12  /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
@@ -88,7 +89,8 @@ enum ao_family {
 
 /* variant flags */
 #define AO_VF_NT_STORE 1      /* non-temporal (streaming) stores of the output */
-#define AO_VF_HALO_PREFETCH 2 /* register z-march: load the next plane's halo a plane ahead */
+#define AO_VF_HALO_PREFETCH 2 /* register z-marches: issue the next plane's loads a plane
+                                 ahead (the halo for one sweep; every load for two) */
 #define AO_VF_OCCUPANCY 4     /* two-sweep z-march: registers capped for 4 waves per SIMD */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lanes.h"
 
 namespace ao {
 namespace {
@@ -124,8 +125,8 @@ __device__ void tile_zreg(const Inst& in, const double* __restrict__ src, double
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double left = __shfl_up(cur[r], 1);
-            const double right = __shfl_down(cur[r], 1);
+            const double left = from_left(cur[r]);
+            const double right = from_right(cur[r]);
             const double xm = (lane == 0) ? ex[r] : left;
             const double xp = (lane == 63) ? ex[r] : right;
             const double ym = (r == 0) ? ymv : cur[r - 1];

@@ -34,6 +34,7 @@
 // the 8 XCDs round-robin, so consecutive logical tiles (which share z- and
 // y-neighbour planes) are remapped to the same XCD and meet in its L2.
 #include "internal.h"
+#include "lanes.h"
 
 namespace ao {
 namespace {
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
         for (int r = 0; r < R; ++r) {
             const int j = j0 + r;
             // x neighbours: within the lane, then across lanes
-            const double left = __shfl_up(cur[r].v[VX - 1], 1);
-            const double right = __shfl_down(cur[r].v[0], 1);
+            const double left = from_left(cur[r].v[VX - 1]);
+            const double right = from_right(cur[r].v[0]);
             const double xl = (lane == 0) ? hc.ex[r] : left;
             const double xr = (lane == 63) ? hc.ex[r] : right;
 #pragma unroll
@@ -266,8 +267,10 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg(const double* __rest
 // k it loads u(k+1), computes v(k) on all 64 lanes (strip edges from lanes 0
 // and 63's extra loads), then w(k-1) = J(v) on lanes 1..62.  v at positions
 // outside the grid is forced to +0.0 -- the ghost value a separate second
-// sweep would read -- so w is bit-identical to two sweeps.
-template <int R, bool NT>
+// sweep would read -- so w is bit-identical to two sweeps.  With PF the
+// loads of plane k+2 (and the strip edges of plane k+1) are issued during
+// iteration k, so an iteration never waits on loads it issued itself.
+template <int R, bool NT, bool PF>
 __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
                                              double* __restrict__ dst, int nx, int ny, int nz,
                                              int nbx, int nby, int bz, unsigned nblocks) {
@@ -308,19 +311,39 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     for (int r = 0; r < R; ++r) vm[r] = 0.0;  // v(k0-3) is never read
 #pragma unroll
     for (int q = 0; q < RV; ++q) vc[q] = 0.0;  // v(k0-2) only feeds w(k0-1), never stored
+    double upn[PF ? RU : 1], exn[PF ? RV : 1];
+    if constexpr (PF) {
+#pragma unroll
+        for (int q = 0; q < RU; ++q) upn[q] = ld(k0, j0 - 2 + q, i, xin);
+#pragma unroll
+        for (int q = 0; q < RV; ++q) exn[q] = ld(k0 - 1, j0 - 1 + q, ie, eok);
+    }
     for (int k = k0 - 1; k <= k1; ++k) {
         double ex[RV];
+        if constexpr (PF) {
 #pragma unroll
-        for (int q = 0; q < RU; ++q) up[q] = ld(k + 1, j0 - 2 + q, i, xin);
+            for (int q = 0; q < RU; ++q) up[q] = upn[q];
 #pragma unroll
-        for (int q = 0; q < RV; ++q) ex[q] = ld(k, j0 - 1 + q, ie, eok);
+            for (int q = 0; q < RV; ++q) ex[q] = exn[q];
+            if (k < k1) {  // wave-uniform; plane k+2 / edges of k+1 for the next iteration
+#pragma unroll
+                for (int q = 0; q < RU; ++q) upn[q] = ld(k + 2, j0 - 2 + q, i, xin);
+#pragma unroll
+                for (int q = 0; q < RV; ++q) exn[q] = ld(k + 1, j0 - 1 + q, ie, eok);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < RU; ++q) up[q] = ld(k + 1, j0 - 2 + q, i, xin);
+#pragma unroll
+            for (int q = 0; q < RV; ++q) ex[q] = ld(k, j0 - 1 + q, ie, eok);
+        }
         // v(k) on rows j0-1 .. j0+R, all lanes
         const bool kin = k >= 0 && k < nz;
 #pragma unroll
         for (int q = 0; q < RV; ++q) {
             const int j = j0 - 1 + q;
             const double c = uc[q + 1];
-            const double left = __shfl_up(c, 1), right = __shfl_down(c, 1);
+            const double left = from_left(c), right = from_right(c);
             const double xm = (lane == 0) ? ex[q] : left;
             const double xp = (lane == 63) ? ex[q] : right;
             double v = xm + xp;
@@ -337,7 +360,7 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
             for (int r = 0; r < R; ++r) {
                 const int j = j0 + r;
                 const double c = vc[r + 1];
-                const double xm = __shfl_up(c, 1), xp = __shfl_down(c, 1);
+                const double xm = from_left(c), xp = from_right(c);
                 double w = xm + xp;
                 w = w + vc[r];
                 w = w + vc[r + 2];
@@ -358,40 +381,40 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     }
 }
 
-template <int R, bool NT>
+template <int R, bool NT, bool PF>
 __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg_t2(const double* __restrict__ src,
                                                                 double* __restrict__ dst, int nx,
                                                                 int ny, int nz, int nbx, int nby,
                                                                 int bz, unsigned nblocks) {
-    zreg_t2_body<R, NT>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+    zreg_t2_body<R, NT, PF>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
 }
 
 // The same kernel compiled for at least 4 waves per SIMD (register budget
 // 128; the compiler may spill a little).
-template <int R, bool NT>
+template <int R, bool NT, bool PF>
 __global__ __launch_bounds__(64 * kZregWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void jac_zreg_t2_occ(const double* __restrict__ src, double* __restrict__ dst, int nx, int ny,
                      int nz, int nbx, int nby, int bz, unsigned nblocks) {
-    zreg_t2_body<R, NT>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+    zreg_t2_body<R, NT, PF>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
 }
 
-template <int R>
+template <int R, bool PF>
 hipError_t launch_zreg_t2(bool nt, bool occ, dim3 grid, hipStream_t s, const double* src,
                           double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
                           unsigned nb) {
     const dim3 block(64 * kZregWaves);
     if (occ && nt)
-        hipLaunchKernelGGL((jac_zreg_t2_occ<R, true>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_t2_occ<R, true, PF>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     else if (occ)
-        hipLaunchKernelGGL((jac_zreg_t2_occ<R, false>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_t2_occ<R, false, PF>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     else if (nt)
-        hipLaunchKernelGGL((jac_zreg_t2<R, true>), grid, block, 0, s, src, dst, nx, ny, nz, nbx,
-                           nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_t2<R, true, PF>), grid, block, 0, s, src, dst, nx, ny, nz,
+                           nbx, nby, bz, nb);
     else
-        hipLaunchKernelGGL((jac_zreg_t2<R, false>), grid, block, 0, s, src, dst, nx, ny, nz, nbx,
-                           nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_t2<R, false, PF>), grid, block, 0, s, src, dst, nx, ny, nz,
+                           nbx, nby, bz, nb);
     return hipGetLastError();
 }
 
@@ -511,10 +534,15 @@ hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, doubl
     if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nb);
     const unsigned u = (unsigned)nb;
-    if (R == 1) return launch_zreg_t2<1>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
-    if (R == 2) return launch_zreg_t2<2>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
-    if (R == 3) return launch_zreg_t2<3>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
-    if (R == 4) return launch_zreg_t2<4>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+    const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
+#define AO_T2(RR)                                                                                \
+    if (R == RR)                                                                                 \
+        return pf ? launch_zreg_t2<RR, true>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, \
+                                             u)                                                  \
+                  : launch_zreg_t2<RR, false>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby,   \
+                                              bz, u);
+    AO_T2(1) AO_T2(2) AO_T2(3) AO_T2(4) AO_T2(6) AO_T2(8) AO_T2(10) AO_T2(12) AO_T2(16)
+#undef AO_T2
     return hipErrorInvalidConfiguration;
 }
 

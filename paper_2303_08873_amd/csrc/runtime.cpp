@@ -160,6 +160,12 @@ bool same_variant(const ao_variant& a, const ao_variant& b) {
            a.bz == b.bz && a.flags == b.flags;
 }
 
+// rows per wave the two-sweep kernel is compiled for
+bool t2_rows_ok(int r) {
+    return r == 1 || r == 2 || r == 3 || r == 4 || r == 6 || r == 8 || r == 10 || r == 12 ||
+           r == 16;
+}
+
 int validate_variant(int kind, const ao_variant& v, int id) {
     const std::string at = "variant " + std::to_string(id) + ": ";
     if (kind == AO_JACOBI7_F64) {
@@ -174,8 +180,9 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2)
             return fail(AO_EINVAL, at + "unknown GPU Jacobi family");
         if (v.family == AO_FAM_JACOBI_ZREG_T2 &&
-            (v.bx != 64 || v.by < 1 || v.by > 4 || v.bz <= 0))
-            return fail(AO_EINVAL, at + "two-sweep z-march needs bx 64, by 1..4, bz > 0");
+            (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
+            return fail(AO_EINVAL,
+                        at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
         if (v.family == AO_FAM_JACOBI_ZREG &&
             ((v.bx != 64 && v.bx != 128) || (v.by != 1 && v.by != 2 && v.by != 4 && v.by != 8) ||
              v.bz <= 0))
@@ -376,8 +383,10 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
             // a single register z-march sweep when S is odd
             const bool pairs = v.family == AO_FAM_JACOBI_ZREG_T2;
             const int L = pairs ? S / 2 + (S % 2) : S;
-            const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, v.by == 3 ? 2 : v.by,
-                                    v.bz, v.flags & AO_VF_NT_STORE};
+            // (its rows per wave: the largest of 1|2|4|8 not above the pair's)
+            const int single_rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
+            const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, single_rows, v.bz,
+                                    v.flags & AO_VF_NT_STORE};
             auto launch = [&](int l, const double* src, double* dst) {
                 if (!pairs) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
                 if (l == 0 && (S % 2)) return jacobi_gpu_sweep(single, src, dst, nx, ny, nz, s);

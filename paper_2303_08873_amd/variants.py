@@ -3,7 +3,8 @@ as categorical variants are numbered from 0 in the order given, Sec. 3.1
 model_output clause)."""
 from __future__ import annotations
 
-from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_NT_STORE, FAM_JACOBI_DIRECT,
+from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE,
+                   FAM_JACOBI_DIRECT,
                    FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T2, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW,
                    FAM_SPMV_WAVE_ROW, Variant)
 
@@ -18,9 +19,9 @@ def jacobi_variants_blocks():
 
 # ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_DIRECT, 32, 4, 1, 0), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
-                    (FAM_JACOBI_ZREG_T2, 64, 3, 32, 0),
-                    (FAM_JACOBI_ZREG_T2, 64, 4, 32, AO_VF_NT_STORE),
-                    (FAM_JACOBI_ZREG_T2, 64, 1, 16, 0)]
+                    (FAM_JACOBI_ZREG_T2, 64, 4, 16, 0),
+                    (FAM_JACOBI_ZREG_T2, 64, 8, 16, AO_VF_NT_STORE),
+                    (FAM_JACOBI_ZREG_T2, 64, 2, 8, AO_VF_HALO_PREFETCH)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
 STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
 

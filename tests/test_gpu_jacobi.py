@@ -147,6 +147,10 @@ def test_zreg_all_shapes(env, orc, shape, S):
 # (rows per wave, planes per block, flags: 1 streaming stores, 4 register cap)
 T2 = [(1, 1, 0), (1, 3, 1), (2, 16, 0), (2, 5, 1), (4, 64, 0), (4, 2, 1), (2, 100, 0), (1, 7, 0),
       (3, 9, 0), (3, 4, 5), (4, 32, 5), (4, 7, 4)]
+# rows 6 and 8, and the prefetching form (flag 2) with every other flag
+T2_MORE = [(6, 1, 0), (6, 5, 1), (8, 3, 0), (8, 32, 1), (1, 1, 2), (2, 3, 3), (3, 16, 2),
+           (4, 32, 3), (4, 2, 7), (6, 9, 2), (8, 7, 3), (3, 5, 6)]
+T2_BIG = [(10, 1, 0), (12, 3, 1), (16, 5, 0), (10, 32, 3), (12, 7, 2), (16, 2, 1), (12, 33, 4)]
 
 
 @pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
@@ -161,21 +165,24 @@ def test_two_sweep_family_all_shapes(env, orc, shape, S):
     want = orc.jacobi7(u0_h, nx, ny, nz, S)
     u0 = torch.from_numpy(u0_h).to(dev)
     out = torch.empty_like(u0)
-    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG_T2, 64, r, bz, fl) for r, bz, fl in T2]
-    h = ao.region_declare_variants(f"gpu_t2_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
-                                   model_type="roundrobin")
-    for resident in (1, 0):
-        if resident:
-            a = ao.jacobi_args(u0, out, nx, ny, nz, S)
-        else:
-            uh = torch.from_numpy(u0_h).pin_memory()
-            oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
-            a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
-        for v in range(len(T2)):
-            (out if resident else oh).fill_(-1.0)
-            ao.region_run(h, a, stream=st, variant=v)
-            torch.cuda.synchronize()
-            _check((out if resident else oh).cpu().numpy(), want)
+    for tag, lst in (("a", T2), ("b", T2_MORE), ("c", T2_BIG)):
+        vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_ZREG_T2, 64, r, bz, fl)
+              for r, bz, fl in lst]
+        h = ao.region_declare_variants(f"gpu_t2{tag}_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                       model_type="roundrobin")
+        for resident in (1, 0):
+            if resident:
+                a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+            else:
+                uh = torch.from_numpy(u0_h).pin_memory()
+                oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
+                a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
+            for v in range(len(lst)):
+                (out if resident else oh).fill_(-1.0)
+                ao.region_run(h, a, stream=st, variant=v)
+                torch.cuda.synchronize()
+                _check((out if resident else oh).cpu().numpy(), want)
+        ao.region_destroy(h)
 
 
 def test_hbm_copy_probe(env):
