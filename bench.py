@@ -112,8 +112,8 @@ def kernel_only(variant: int, launches: int = 3):
     for _ in range(5):
         ao.ao_hbm_copy(u0, b, n ** 3, stream=stream)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_only": variant, "launches": launches * SWEEPS, "copies": 5,
-                      "copy_bytes_each": 16 * n ** 3}), flush=True)
+    print(json.dumps({"kernel_only": variant, "region_runs": launches, "sweeps_each": SWEEPS,
+                      "copies": 5, "copy_bytes_each": 16 * n ** 3}), flush=True)
 
 
 def batch_workload(steps: int, warmup: int):
@@ -394,14 +394,17 @@ def main():
 
     nbig = SIZES[-1]
     vbig = ao.jacobi_variants_sweep()[chosen[nbig]]
-    # a two-sweep launch carries two sweeps' algorithmic bytes
-    per_launch_sweeps = 2 if vbig.family == ao.FAM_JACOBI_ZREG_T2 else 1
-    launches = SWEEPS // per_launch_sweeps + SWEEPS % per_launch_sweeps
-    per_launch_ms = sorted(big_ms)[len(big_ms) // 2] / launches
+    # a launch of a temporally blocked family carries P sweeps' algorithmic
+    # bytes; the time per launch is the region time per P sweeps (exact when
+    # P divides the sweep count, as it does for P = 1, 2, 4 at 20 sweeps)
+    per_launch_sweeps = {ao.FAM_JACOBI_ZREG_T2: 2, ao.FAM_JACOBI_ZREG_T3: 3,
+                         ao.FAM_JACOBI_ZREG_T4: 4}.get(vbig.family, 1)
+    per_launch_ms = sorted(big_ms)[len(big_ms) // 2] * per_launch_sweeps / SWEEPS
     per_launch_bytes = 16 * nbig ** 3 * per_launch_sweeps
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     vkey = f"family={vbig.family} bx={vbig.bx} by={vbig.by} bz={vbig.bz} flags={vbig.flags}"
     traffic = pmc_traffic(vkey)
+    traffic_gbs = traffic / (per_launch_ms * 1e-3) / 1e9 if traffic else None
     res = {
         "metric": "region GB/s (% HBM peak): learned vs exhaustive selection; selector regret %",
         "value": round(value, 2),
@@ -434,6 +437,8 @@ def main():
                      "kernel": f"variant {chosen[nbig]} ({vkey}) sweep at {nbig}^3",
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "sweeps_per_launch": per_launch_sweeps,
+                     "traffic_gbs": round(traffic_gbs, 1) if traffic_gbs else None,
+                     "traffic_frac": round(traffic_gbs / HBM_PEAK_GBS, 4) if traffic_gbs else None,
                      "per_launch_us": round(per_launch_ms * 1e3, 2)},
     }
     res["largest_size_pct_of_copy_probe"] = round(100.0 * res["largest_size_gbs"] / copy_gbs, 2)

@@ -82,6 +82,12 @@ enum ao_family {
                                   (temporal blocking); bx = 64, by (1|2|3|4|6|8|10|12|16)
                                   rows per wave, bz planes; an odd sweep count adds one
                                   single sweep */
+    AO_FAM_JACOBI_ZREG_T3 = 5, /* GPU: the same with three sweeps fused per pass; bx = 64,
+                                  by (1|2|3|4|6|8) rows per wave, bz planes; S mod 3 sweeps
+                                  run first as one single or one two-sweep pass */
+    AO_FAM_JACOBI_ZREG_T4 = 6, /* GPU: four sweeps fused per pass; bx = 64, by (1|2|3|4),
+                                  bz planes; S mod 4 sweeps run first as one single, two-
+                                  or three-sweep pass */
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
     AO_FAM_SPMV_MERGE_PATH = 12  /* GPU: nnz-balanced row-aligned chunks, blocks of bx */

@@ -15,6 +15,8 @@ AO_JACOBI7_F64, AO_CSR_SPMV_F64 = 0, 1
 AO_TARGET_GPU, AO_TARGET_HOST = 0, 1
 FAM_JACOBI_DIRECT, FAM_JACOBI_ZMARCH, FAM_JACOBI_HOST, FAM_JACOBI_ZREG = 0, 1, 2, 3
 FAM_JACOBI_ZREG_T2 = 4
+FAM_JACOBI_ZREG_T3 = 5
+FAM_JACOBI_ZREG_T4 = 6
 FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH = 10, 11, 12
 AO_VF_NT_STORE = 1
 AO_VF_HALO_PREFETCH = 2

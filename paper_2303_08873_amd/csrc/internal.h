@@ -24,6 +24,9 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
 // Two sweeps at once (temporal-blocking family): dst <- J(J(src)).
 hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, double* dst, int nx,
                                   int ny, int nz, hipStream_t s);
+// Three or four sweeps at once (families ZREG_T3 / ZREG_T4): dst <- J^T(src).
+hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double* dst, int nx,
+                                 int ny, int nz, hipStream_t s);
 hipError_t hbm_copy(const double* src, double* dst, int64_t n, bool nt, hipStream_t s);
 
 // Host (OpenMP) variant: S sweeps from u0 into out using tmp (N doubles) as

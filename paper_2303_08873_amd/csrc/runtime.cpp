@@ -177,12 +177,21 @@ int validate_variant(int kind, const ao_variant& v, int id) {
         }
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "unknown target");
         if (v.family != AO_FAM_JACOBI_DIRECT && v.family != AO_FAM_JACOBI_ZMARCH &&
-            v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2)
+            v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2 &&
+            v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4)
             return fail(AO_EINVAL, at + "unknown GPU Jacobi family");
         if (v.family == AO_FAM_JACOBI_ZREG_T2 &&
             (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL,
                         at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
+        if (v.family == AO_FAM_JACOBI_ZREG_T3 &&
+            (v.bx != 64 || !(v.by == 1 || v.by == 2 || v.by == 3 || v.by == 4 || v.by == 6 ||
+                             v.by == 8) ||
+             v.bz <= 0))
+            return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1|2|3|4|6|8, bz > 0");
+        if (v.family == AO_FAM_JACOBI_ZREG_T4 &&
+            (v.bx != 64 || v.by < 1 || v.by > 4 || v.bz <= 0))
+            return fail(AO_EINVAL, at + "four-sweep z-march needs bx 64, by 1..4, bz > 0");
         if (v.family == AO_FAM_JACOBI_ZREG &&
             ((v.bx != 64 && v.bx != 128) || (v.by != 1 && v.by != 2 && v.by != 4 && v.by != 8) ||
              v.bz <= 0))
@@ -379,18 +388,31 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
             if (rc) return rc;
             hipEvent_t e0 = get_event(r), e1 = get_event(r);
             if (!e0 || !e1) return fail(AO_EHIP, "event creation failed");
-            // launches: one per sweep, or (two-sweep family) one per pair plus
-            // a single register z-march sweep when S is odd
-            const bool pairs = v.family == AO_FAM_JACOBI_ZREG_T2;
-            const int L = pairs ? S / 2 + (S % 2) : S;
-            // (its rows per wave: the largest of 1|2|4|8 not above the pair's)
+            // launches: one per sweep, or (families fusing P = 2, 3 or 4
+            // sweeps per pass) one per P sweeps, the S mod P remaining sweeps
+            // first as one single register z-march sweep, one two-sweep or one
+            // three-sweep pass
+            const int P = v.family == AO_FAM_JACOBI_ZREG_T2   ? 2
+                          : v.family == AO_FAM_JACOBI_ZREG_T3 ? 3
+                          : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4
+                                                              : 1;
+            const int rem = S % P;
+            const int L = S / P + (rem ? 1 : 0);
+            // (its rows per wave: the largest of 1|2|4|8 not above the variant's)
             const int single_rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
             const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, single_rows, v.bz,
                                     v.flags & AO_VF_NT_STORE};
+            const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, v.by, v.bz,
+                                 v.flags & AO_VF_NT_STORE};
+            const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, v.by, v.bz,
+                                   v.flags & AO_VF_NT_STORE};
             auto launch = [&](int l, const double* src, double* dst) {
-                if (!pairs) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
-                if (l == 0 && (S % 2)) return jacobi_gpu_sweep(single, src, dst, nx, ny, nz, s);
-                return jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s);
+                if (P == 1) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
+                if (l == 0 && rem == 1) return jacobi_gpu_sweep(single, src, dst, nx, ny, nz, s);
+                if (l == 0 && rem == 2) return jacobi_gpu_double_sweep(two, src, dst, nx, ny, nz, s);
+                if (l == 0 && rem == 3) return jacobi_gpu_multi_sweep(three, src, dst, nx, ny, nz, s);
+                return P == 2 ? jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s)
+                              : jacobi_gpu_multi_sweep(v, src, dst, nx, ny, nz, s);
             };
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess && n > 0) {

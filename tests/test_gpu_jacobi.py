@@ -185,6 +185,43 @@ def test_two_sweep_family_all_shapes(env, orc, shape, S):
         ao.region_destroy(h)
 
 
+T3 = [(1, 1, 0), (1, 5, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2, 0), (4, 16, 1),
+      (6, 9, 0), (6, 1, 1), (8, 4, 0), (8, 32, 1)]
+T4 = [(1, 1, 0), (1, 6, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2, 0), (4, 16, 1),
+      (4, 5, 1), (2, 1, 0)]
+
+
+@pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
+                                     ((257, 3, 4), 1), ((64, 32, 16), 6), ((6, 6, 6), 5),
+                                     ((61, 5, 7), 7), ((125, 18, 33), 9), ((60, 60, 3), 8)])
+def test_three_and_four_sweep_families_all_shapes(env, orc, shape, S):
+    # three / four sweeps fused per pass (the S mod T remaining sweeps first as
+    # one shorter pass), bit-identical to S separate sweeps
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=71 + nx + S)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    for fam, lst in ((ao.FAM_JACOBI_ZREG_T3, T3), (ao.FAM_JACOBI_ZREG_T4, T4)):
+        vs = [ao.Variant(ao.AO_TARGET_GPU, fam, 64, r, bz, fl) for r, bz, fl in lst]
+        h = ao.region_declare_variants(f"gpu_tb{fam}_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                       model_type="roundrobin")
+        for resident in (1, 0):
+            if resident:
+                a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+            else:
+                uh = torch.from_numpy(u0_h).pin_memory()
+                oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
+                a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
+            for v in range(len(lst)):
+                (out if resident else oh).fill_(-1.0)
+                ao.region_run(h, a, stream=st, variant=v)
+                torch.cuda.synchronize()
+                _check((out if resident else oh).cpu().numpy(), want)
+        ao.region_destroy(h)
+
+
 def test_hbm_copy_probe(env):
     ao, torch, dev, st = env
     for n in (0, 1, 5, 4096, 1000003):

@@ -115,6 +115,26 @@ def test_argument_errors(ao):
                                    model_type="forest")
     with pytest.raises(ao.AdaptError):
         ao.region_declare_variants("toomany", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep() * 2)
+    # z-march families accept only the row counts they are compiled for
+    G = ao.AO_TARGET_GPU
+    for fam, rows in ((ao.FAM_JACOBI_ZREG, (3, 16)), (ao.FAM_JACOBI_ZREG_T2, (5, 7, 9, 32)),
+                      (ao.FAM_JACOBI_ZREG_T3, (5, 10, 12, 16)), (ao.FAM_JACOBI_ZREG_T4, (5, 6, 8))):
+        for r in rows:
+            with pytest.raises(ao.AdaptError):
+                ao.region_declare_variants(f"rows_{fam}_{r}", ao.AO_JACOBI7_F64,
+                                           [ao.Variant(G, fam, 64, r, 8, 0)])
+        with pytest.raises(ao.AdaptError):  # strip width other than 64
+            ao.region_declare_variants(f"width_{fam}", ao.AO_JACOBI7_F64,
+                                       [ao.Variant(G, fam, 32, 2, 8, 0)])
+        with pytest.raises(ao.AdaptError):  # no planes per block
+            ao.region_declare_variants(f"bz_{fam}", ao.AO_JACOBI7_F64,
+                                       [ao.Variant(G, fam, 64, 2, 0, 0)])
+    ok = [ao.Variant(G, ao.FAM_JACOBI_ZREG_T2, 64, r, 8, 0) for r in (1, 2, 3, 4, 6, 8, 10, 12, 16)]
+    ao.region_destroy(ao.region_declare_variants("t2rows", ao.AO_JACOBI7_F64, ok))
+    ok = [ao.Variant(G, ao.FAM_JACOBI_ZREG_T3, 64, r, 8, 1) for r in (1, 2, 3, 4, 6, 8)]
+    ao.region_destroy(ao.region_declare_variants("t3rows", ao.AO_JACOBI7_F64, ok))
+    ok = [ao.Variant(G, ao.FAM_JACOBI_ZREG_T4, 64, r, 8, 1) for r in (1, 2, 3, 4)]
+    ao.region_destroy(ao.region_declare_variants("t4rows", ao.AO_JACOBI7_F64, ok))
     ao.region_destroy(h)
 
 
