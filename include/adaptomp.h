@@ -251,15 +251,32 @@ int batch_create(const ao_args* inst, int count, ao_batch** out);
  * empty bucket).  Synchronises; overwrites the instances' outputs. */
 int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen);
 
-/* Run every instance once: one persistent kernel per sweep over the work
- * list.  use_graph != 0 launches the sweeps as one captured HIP graph
- * (captured on first use, re-captured after autotuning).  Enqueued on
+/* Run every instance once: one persistent kernel per pass over the work
+ * list -- a pass is one sweep, or two sweeps on the fused tiles (the first
+ * pass of an odd sweep count is then a single sweep), so an instance on a
+ * fused tile takes ceil(S/2) passes.  Fused tiles run in a second
+ * persistent kernel launched beside the first in each pass.  use_graph != 0
+ * launches all passes as one captured HIP graph (captured on first use,
+ * re-captured after autotuning or batch_set_tiles).  Enqueued on
  * `stream`. */
 int batch_run(ao_batch* b, void* stream, int use_graph);
 
 /* Per-bucket information: number of instances, work items and the tile
- * (tx, ty, tz) in use, 5 buckets each, any pointer may be NULL. */
+ * (tx, ty, tz) in use, 5 buckets each, any pointer may be NULL.  For a
+ * fused tile tx = 62 (columns stored per 64-lane strip). */
 int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz);
+
+/* The candidate tile table the autotuner searches: returns its length and,
+ * when tiles is not NULL, writes (kind, tx, ty, tz) per candidate into
+ * tiles[4 * length]; kind 0 = one point per thread, 1|2|4 = register
+ * z-march with that many rows per wave, 11|12|14 = fused two-sweep
+ * z-march with 1|2|4 rows per wave. */
+int batch_candidates(int* tiles);
+
+/* Fix the tile of each bucket: cand[5] candidate indices, -1 keeps the
+ * bucket's current tile.  AO_EINVAL for an index outside the table (the
+ * plan is unchanged). */
+int batch_set_tiles(ao_batch* b, const int* cand);
 
 int batch_destroy(ao_batch* b);
 

@@ -17,7 +17,8 @@ from ._lib import (  # noqa: F401
     FAM_JACOBI_ZREG_T4,
     FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, AdaptError, Args, Stats,
     TrainOpts, Variant, lib, lib_path, ao_last_error, ao_device_cus, ao_hbm_copy, ao_mlp_adam, ao_mlp_forward,
-    ao_mlp_grad, batch_autotune, batch_create, batch_destroy, batch_info, batch_run,
+    ao_mlp_grad, batch_autotune, batch_candidates, batch_create, batch_destroy, batch_info,
+    batch_run, batch_set_tiles,
     region_clear_memo, region_declare_variants, region_destroy, region_features, region_load, region_profile,
     region_record, region_records, region_run, region_save, region_stats, selector_select, selector_train,
     jacobi_args, spmv_args)

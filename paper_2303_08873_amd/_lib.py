@@ -94,6 +94,8 @@ def _load():
         "batch_autotune": [P, P, I, I, P],
         "batch_run": [P, P, I],
         "batch_info": [P, P, P, P],
+        "batch_candidates": [P],
+        "batch_set_tiles": [P, P],
         "batch_destroy": [P],
         "ao_mlp_forward": [P, P, I, P, P],
         "ao_mlp_grad": [P, P, P, P, I, P, P, P],
@@ -278,6 +280,18 @@ def batch_info(batch):
     tiles = (ctypes.c_int * 15)()
     _check(lib.batch_info(batch, inst, items, tiles))
     return list(inst), list(items), [tuple(tiles[3 * b:3 * b + 3]) for b in range(5)]
+
+
+def batch_candidates():
+    n = lib.batch_candidates(None)
+    tiles = (ctypes.c_int * (4 * n))()
+    lib.batch_candidates(tiles)
+    return [tuple(tiles[4 * c:4 * c + 4]) for c in range(n)]
+
+
+def batch_set_tiles(batch, cand) -> None:
+    arr = (ctypes.c_int * 5)(*cand)
+    _check(lib.batch_set_tiles(batch, arr))
 
 
 def batch_destroy(batch) -> None:

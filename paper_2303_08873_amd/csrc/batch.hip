@@ -14,7 +14,12 @@
 //  direct  tx*ty*tz points, threads stride over them, six neighbour loads
 //          each (small grids, where a 64-wide strip would idle lanes);
 //  zreg    the register z-march: each of the 4 waves owns a 64-wide strip of
-//          R rows and marches tz planes, x-neighbours by cross-lane moves.
+//          R rows and marches tz planes, x-neighbours by cross-lane moves;
+//  fused   the register z-march with two sweeps fused per pass (zmarch.h):
+//          64 lanes, 62 stored columns, R rows per wave.  An instance on a
+//          fused tile runs ceil(S/2) passes, the first one a single sweep
+//          on the same tile when S is odd.  Fused tiles run in a kernel of
+//          their own (it needs more registers than the others).
 #include <math.h>
 
 #include <algorithm>
@@ -23,6 +28,7 @@
 
 #include "internal.h"
 #include "lanes.h"
+#include "zmarch.h"
 
 namespace ao {
 namespace {
@@ -31,7 +37,8 @@ constexpr double kC = 0x1.5555555555555p-3;  // fl(1/6)
 constexpr int kThreads = 256;
 constexpr int kBuckets = 5;
 
-enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2, kZreg4 = 4 };
+enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2, kZreg4 = 4, kFused1 = 11, kFused2 = 12, kFused4 = 14 };
+__host__ __device__ constexpr bool is_fused(int kind) { return kind > 10; }
 struct TileCfg {
     int kind, tx, ty, tz;
 };
@@ -41,10 +48,13 @@ constexpr TileCfg kCands[] = {
     {kDirect, 64, 4, 1}, {kDirect, 16, 16, 4}, {kDirect, 8, 8, 16},  {kZreg1, 64, 4, 16},
     {kZreg2, 64, 8, 32}, {kZreg2, 64, 8, 64},  {kZreg1, 64, 4, 64},  {kZreg2, 64, 8, 16},
     {kZreg4, 64, 16, 24}, {kZreg4, 64, 16, 32}, {kZreg4, 64, 16, 64}, {kZreg2, 64, 8, 24},
+    {kFused1, 62, 4, 16}, {kFused2, 62, 8, 16},  {kFused2, 62, 8, 32},  {kFused4, 62, 16, 16},
+    {kFused4, 62, 16, 32}, {kFused1, 62, 4, 32},
 };
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 // default candidate per bucket before autotuning
-constexpr int kDefaultCand[kBuckets] = {0, 1, 3, 8, 8};
+constexpr int kDefaultCand[kBuckets] = {0, 3, 6, 19, 19};
+static_assert(kCands[19].kind == kFused4 && kCands[19].tz == 16, "default tile of the large buckets");
 __constant__ TileCfg c_cands[kNumCands];
 
 struct Item {
@@ -56,6 +66,12 @@ struct Inst {
     double* tmp;
     int32_t nx, ny, nz, sweeps;
 };
+
+// launches an instance takes on a tile kind: one per sweep, or one per pair
+// of sweeps on fused tiles
+__host__ __device__ inline int passes_of(int sweeps, int kind) {
+    return is_fused(kind) ? (sweeps + 1) / 2 : sweeps;
+}
 
 __device__ __forceinline__ const double* src_of(const Inst& in, int s) {
     return s == 0 ? in.u0 : (((in.sweeps - s) % 2 == 0) ? in.out : in.tmp);
@@ -178,6 +194,48 @@ __global__ __launch_bounds__(kThreads) void k_batch_sweep(const Inst* __restrict
     }
 }
 
+// Pass `pass` of every instance on a fused tile: ping-pong over ceil(S/2)
+// passes so the last one lands in `out`; pass 0 is a single sweep when S is
+// odd.  Strip x0 (a multiple of 62) is computed on lanes x0-1 .. x0+62.
+__global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict__ insts,
+                                                          const Item* __restrict__ items,
+                                                          int nitems, int pass) {
+    const int g = (int)gridDim.x;
+    const int slot = xcd_slot((int)blockIdx.x, g);
+    const int wave = (int)(threadIdx.x >> 6);
+    for (int w = slot; w < nitems; w += g) {
+        const Item it = items[w];
+        const Inst in = insts[it.inst];
+        const int P = passes_of(in.sweeps, kFused1);
+        if (pass >= P) continue;
+        const TileCfg c = c_cands[it.cand];
+        const double* src = pass == 0 ? in.u0 : (((P - pass) % 2 == 0) ? in.out : in.tmp);
+        double* dst = ((P - 1 - pass) % 2 == 0) ? in.out : in.tmp;
+        const bool single = (in.sweeps & 1) && pass == 0;
+        const int R = c.kind - 10;
+        const int j0 = it.y0 + wave * R;
+        if (j0 >= in.ny) continue;  // wave-uniform
+        const int k1 = min(in.nz, it.z0 + c.tz);
+        const int i0 = it.x0 - 1;
+        if (R == 1) {
+            if (single)
+                zm::tb_column<1, 1, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+            else
+                zm::tb_column<2, 1, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+        } else if (R == 2) {
+            if (single)
+                zm::tb_column<1, 2, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+            else
+                zm::tb_column<2, 2, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+        } else {
+            if (single)
+                zm::tb_column<1, 4, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+            else
+                zm::tb_column<2, 4, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+        }
+    }
+}
+
 int bucket_of(int nx, int ny, int nz) {
     const int m = std::max(nx, std::max(ny, nz));
     if (m <= 16) return 0;
@@ -201,10 +259,13 @@ struct ao_batch {
     std::vector<Inst> insts;
     std::vector<int> bucket;
     int cand[kBuckets];
-    int max_sweeps = 0;
     Inst* d_insts = nullptr;
-    Item* d_items = nullptr;
+    Item* d_items = nullptr;   // single-sweep tiles (direct, zreg)
     int nitems = 0;
+    int launches = 0;          // passes of the single-sweep tiles
+    Item* d_items_f = nullptr;  // fused tiles
+    int nitems_f = 0;
+    int launches_f = 0;
     int items_per_bucket[kBuckets] = {0};
     double* scratch = nullptr;
     int grid = 0;
@@ -217,6 +278,7 @@ struct ao_batch {
         if (graph) hipGraphDestroy(graph);
         if (cap_stream) hipStreamDestroy(cap_stream);
         if (d_items) hipFree(d_items);
+        if (d_items_f) hipFree(d_items_f);
         if (d_insts) hipFree(d_insts);
         if (scratch) hipFree(scratch);
     }
@@ -247,14 +309,35 @@ std::vector<Item> make_items(const ao_batch* b, int only_bucket, int cand_overri
     return out;
 }
 
-hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
-    if (b->d_items) hipFree(b->d_items);
-    b->d_items = nullptr;
-    b->nitems = (int)items.size();
+hipError_t upload_list(Item** d, int* count, const std::vector<Item>& items) {
+    if (*d) hipFree(*d);
+    *d = nullptr;
+    *count = (int)items.size();
     if (items.empty()) return hipSuccess;
-    hipError_t e = hipMalloc(&b->d_items, items.size() * sizeof(Item));
+    hipError_t e = hipMalloc(d, items.size() * sizeof(Item));
     if (e == hipSuccess)
-        e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
+        e = hipMemcpy(*d, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
+    return e;
+}
+
+// Splits the work list by kernel (single-sweep tiles / fused tiles) and
+// counts the launches each kernel needs.
+hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
+    std::vector<Item> single, fused;
+    b->launches = b->launches_f = 0;
+    for (const Item& it : items) {
+        const int kind = kCands[it.cand].kind;
+        const int P = passes_of(b->insts[it.inst].sweeps, kind);
+        if (is_fused(kind)) {
+            fused.push_back(it);
+            b->launches_f = std::max(b->launches_f, P);
+        } else {
+            single.push_back(it);
+            b->launches = std::max(b->launches, P);
+        }
+    }
+    hipError_t e = upload_list(&b->d_items, &b->nitems, single);
+    if (e == hipSuccess) e = upload_list(&b->d_items_f, &b->nitems_f, fused);
     return e;
 }
 
@@ -266,11 +349,14 @@ hipError_t launch_sweeps(ao_batch* b, hipStream_t s) {
             if (e != hipSuccess) return e;
         }
     }
-    if (b->nitems == 0) return hipSuccess;
-    const int grid = std::min(b->nitems, b->grid);
-    for (int sw = 0; sw < b->max_sweeps; ++sw) {
-        hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kThreads), 0, s, b->d_insts, b->d_items,
-                           b->nitems, sw);
+    const int grid = std::min(b->nitems, b->grid), grid_f = std::min(b->nitems_f, b->grid);
+    for (int l = 0; l < std::max(b->launches, b->launches_f); ++l) {
+        if (l < b->launches && b->nitems > 0)
+            hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kThreads), 0, s, b->d_insts,
+                               b->d_items, b->nitems, l);
+        if (l < b->launches_f && b->nitems_f > 0)
+            hipLaunchKernelGGL(k_batch_fused, dim3(grid_f), dim3(kThreads), 0, s, b->d_insts,
+                               b->d_items_f, b->nitems_f, l);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -327,7 +413,6 @@ int batch_create(const ao_args* inst, int count, ao_batch** out) {
         off += (size_t)a.nx * a.ny * a.nz;
         b->insts.push_back(in);
         b->bucket.push_back(bucket_of(a.nx, a.ny, a.nz));
-        b->max_sweeps = std::max(b->max_sweeps, a.sweeps);
     }
     for (int k = 0; k < kBuckets; ++k) b->cand[k] = kDefaultCand[k];
     e = hipMalloc(&b->d_insts, b->insts.size() * sizeof(Inst));
@@ -446,6 +531,27 @@ int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz) {
         }
     }
     return AO_OK;
+}
+
+int batch_candidates(int* tiles) {
+    if (tiles)
+        for (int c = 0; c < kNumCands; ++c) {
+            tiles[4 * c] = kCands[c].kind;
+            tiles[4 * c + 1] = kCands[c].tx;
+            tiles[4 * c + 2] = kCands[c].ty;
+            tiles[4 * c + 3] = kCands[c].tz;
+        }
+    return kNumCands;
+}
+
+int batch_set_tiles(ao_batch* b, const int* cand) {
+    if (!b || !cand) return fail(AO_EINVAL, "batch or cand is NULL");
+    for (int k = 0; k < kBuckets; ++k)
+        if (cand[k] < -1 || cand[k] >= kNumCands)
+            return fail(AO_EINVAL, "tile candidate index out of range");
+    for (int k = 0; k < kBuckets; ++k)
+        if (cand[k] >= 0) b->cand[k] = cand[k];
+    return rebuild(b);
 }
 
 int batch_destroy(ao_batch* b) {

@@ -35,6 +35,7 @@
 // y-neighbour planes) are remapped to the same XCD and meet in its L2.
 #include "internal.h"
 #include "lanes.h"
+#include "zmarch.h"
 
 namespace ao {
 namespace {
@@ -399,127 +400,24 @@ void jac_zreg_t2_occ(const double* __restrict__ src, double* __restrict__ dst, i
 }
 
 // T sweeps per pass (temporal blocking factor T >= 2), the two-sweep scheme
-// generalised.  Level l holds the values after l sweeps (level 0 = input).
-// A wave owns 64 lanes of x starting at i0 = (66 - 2T)*bi - (T - 1) and R
-// output rows from j0; level l lives on NL(l) = R + 2(T - l) rows from
-// j0 - (T - l).  In iteration k the wave loads level 0 at plane k+1, then
-// computes level l at plane k - l + 1 for l = 1..T from level l-1 on planes
-// k-l .. k-l+2: the plane below (kept for the centre rows of level l), the
-// centre plane and the plane just computed.  Level 1 takes its strip edges
-// from lanes 0 and 63's extra loads; level l is exact on lanes l-1 .. 64-l,
-// so level T is stored on lanes T-1 .. 64-T (66 - 2T points per strip).
-// Every level below T is forced to +0.0 outside the grid -- the ghost value
-// a separate sweep would read -- so the result is bit-identical to T sweeps.
-// Planes computed before a level's inputs are loaded only feed planes that
-// are never stored.
-template <int T, int R>
-struct TbShape {
-    static constexpr int nl(int l) { return R + 2 * (T - l); }
-    // offset of level l in the packed centre / fresh arrays: sum of nl(0..l-1)
-    static constexpr int off(int l) { return l * (R + 2 * T) - l * (l - 1); }
-    // offset of level l in the packed below array (rows of level l+1): sum
-    // of nl(1..l)
-    static constexpr int offm(int l) { return l * (R + 2 * T) - l * (l + 1); }
-    static constexpr int kAll = off(T);
-    static constexpr int kBelow = offm(T);
-};
-
-// One level of the T-sweep pass: level L at plane p from level L-1, then
-// the next level.  The arrays are the caller's register arrays; every index
-// is a compile-time constant once inlined, so they stay in registers.
-template <int T, int R, int L, bool NT>
-__device__ __forceinline__ void tb_level(const double* below, const double* centre,
-                                         double* fresh, const double* ex, double* dst,
-                                         int k, int j0, int nx, int ny, int nz, int k0, int k1,
-                                         size_t plane, int lane, int i, bool xin, bool lane_out) {
-    using S = TbShape<T, R>;
-    const int p = k - L + 1;
-    if (L == T && !(p >= k0 && p < k1)) return;  // wave-uniform
-    const int jl = j0 - (T - L);
-    const bool pin = p >= 0 && p < nz;
-#pragma unroll
-    for (int q = 0; q < S::nl(L); ++q) {
-        const int j = jl + q;
-        const double c = centre[S::off(L - 1) + q + 1];
-        const double left = from_left(c), right = from_right(c);
-        const double xm = (L == 1 && lane == 0) ? ex[q] : left;
-        const double xp = (L == 1 && lane == 63) ? ex[q] : right;
-        double v = xm + xp;
-        v = v + centre[S::off(L - 1) + q];
-        v = v + centre[S::off(L - 1) + q + 2];
-        v = v + below[S::offm(L - 1) + q];
-        v = v + fresh[S::off(L - 1) + q + 1];
-        if constexpr (L < T) {
-            fresh[S::off(L) + q] = (pin && xin && j >= 0 && j < ny) ? v * kC : 0.0;
-        } else {
-            if (lane_out && j < ny) store<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kC);
-        }
-    }
-    if constexpr (L < T)
-        tb_level<T, R, L + 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                                  lane, i, xin, lane_out);
-}
-
-// Shift every level by one plane: below <- centre (centre rows of the next
-// level), centre <- fresh.
-template <int T, int R, int L>
-__device__ __forceinline__ void tb_rotate(double* below, double* centre, const double* fresh) {
-    using S = TbShape<T, R>;
-#pragma unroll
-    for (int q = 0; q < S::nl(L + 1); ++q) below[S::offm(L) + q] = centre[S::off(L) + q + 1];
-#pragma unroll
-    for (int q = 0; q < S::nl(L); ++q) centre[S::off(L) + q] = fresh[S::off(L) + q];
-    if constexpr (L + 1 < T) tb_rotate<T, R, L + 1>(below, centre, fresh);
-}
-
+// generalised: one wave runs tb_column (zmarch.h) on its 64-lane strip,
+// starting at i0 = (66 - 2T)*bi - (T - 1), storing lanes T-1 .. 64-T.
 template <int T, int R, bool NT>
 __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
                                              double* __restrict__ dst, int nx, int ny, int nz,
                                              int nbx, int nby, int bz, unsigned nblocks) {
-    using S = TbShape<T, R>;
     constexpr int W = 66 - 2 * T;
     const unsigned b = xcd_remap(blockIdx.x, nblocks);
     const int bi = (int)(b % (unsigned)nbx);
     const unsigned t = b / (unsigned)nbx;
     const int bj = (int)(t % (unsigned)nby);
     const int kb = (int)(t / (unsigned)nby);
-    const int lane = (int)(threadIdx.x & 63);
     const int wave = (int)(threadIdx.x >> 6);
-    const int i0 = W * bi - (T - 1);
-    const int i = i0 + lane;
     const int j0 = (bj * kZregWaves + wave) * R;
     if (j0 >= ny) return;  // wave-uniform
     const int k0 = kb * bz;
-    const int k1 = min(nz, k0 + bz);
-    const size_t plane = (size_t)nx * (size_t)ny;
-    const bool xin = i >= 0 && i < nx;
-    const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
-    const bool eok = (lane == 0 || lane == 63) && ie >= 0 && ie < nx;
-    const bool lane_out = lane >= T - 1 && lane <= 64 - T && xin;
-    auto ld = [&](int k, int j, int x, bool ok) -> double {
-        return (ok && k >= 0 && k < nz && j >= 0 && j < ny) ? src[(size_t)k * plane + (size_t)j * nx + x]
-                                                          : 0.0;
-    };
-    double below[S::kBelow], centre[S::kAll], fresh[S::kAll];
-    const int ka = k0 - T + 1;  // first iteration: level 1 at plane ka
-#pragma unroll
-    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, i, xin);
-#pragma unroll
-    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, i, xin);
-#pragma unroll
-    for (int q = S::nl(1); q < S::kBelow; ++q) below[q] = 0.0;
-#pragma unroll
-    for (int q = S::nl(0); q < S::kAll; ++q) centre[q] = 0.0;
-    for (int k = ka; k <= k1 + T - 2; ++k) {
-        double ex[S::nl(1)];
-#pragma unroll
-        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, i, xin);
-#pragma unroll
-        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, ie, eok);
-        tb_level<T, R, 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                              lane, i, xin, lane_out);
-        tb_rotate<T, R, 0>(below, centre, fresh);
-    }
+    zm::tb_column<T, R, NT>(src, dst, nx, ny, nz, W * bi - (T - 1), j0, k0, min(nz, k0 + bz), T - 1,
+                        64 - T);
 }
 
 template <int T, int R, bool NT>

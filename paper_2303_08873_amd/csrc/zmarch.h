@@ -1,0 +1,141 @@
+// The register z-march with T sweeps fused per pass, for one wave: shared by
+// the per-grid kernels and the batched kernel (device code only).
+//
+// Level l holds the values after l sweeps (level 0 = input).  The wave owns
+// 64 lanes of x starting at i0 and the output rows j0 .. j0+R-1; level l
+// lives on NL(l) = R + 2(T - l) rows from j0 - (T - l).  In iteration k the
+// wave loads level 0 at plane k+1, then computes level l at plane k - l + 1
+// for l = 1..T from level l-1 on planes k-l .. k-l+2: the plane below (kept
+// only for the centre rows of level l), the centre plane and the plane just
+// computed.  Level 1 takes its strip edges from lanes 0 and 63's extra loads;
+// level l is exact on lanes l-1 .. 64-l.  Every level below T is forced to
+// +0.0 outside the grid -- the ghost value a separate sweep would read -- so
+// the result is bit-identical to T separate sweeps.  Planes computed before
+// a level's inputs are loaded only feed planes that are never stored.  The
+// sum order is the region's ((((xm+xp)+ym)+yp)+zm)+zp, then one multiply by
+// fl(1/6).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lanes.h"
+
+namespace ao {
+namespace zm {
+
+constexpr double kSixth = 0x1.5555555555555p-3;  // fl(1/6)
+
+template <bool NT>
+__device__ __forceinline__ void put(double* p, double v) {
+    if constexpr (NT) {
+        __builtin_nontemporal_store(v, p);
+    } else {
+        *p = v;
+    }
+}
+
+template <int T, int R>
+struct TbShape {
+    static constexpr int nl(int l) { return R + 2 * (T - l); }
+    // offset of level l in the packed centre / fresh arrays: sum of nl(0..l-1)
+    static constexpr int off(int l) { return l * (R + 2 * T) - l * (l - 1); }
+    // offset of level l in the packed below array (rows of level l+1): sum
+    // of nl(1..l)
+    static constexpr int offm(int l) { return l * (R + 2 * T) - l * (l + 1); }
+    static constexpr int kAll = off(T);
+    static constexpr int kBelow = offm(T);
+};
+
+// One level: level L at plane p from level L-1, then the next level.  The
+// arrays are the caller's register arrays; every index is a compile-time
+// constant once inlined, so they stay in registers.
+template <int T, int R, int L, bool NT>
+__device__ __forceinline__ void tb_level(const double* below, const double* centre,
+                                         double* fresh, const double* ex, double* dst,
+                                         int k, int j0, int nx, int ny, int nz, int k0, int k1,
+                                         size_t plane, int lane, int i, bool xin, bool lane_out) {
+    using S = TbShape<T, R>;
+    const int p = k - L + 1;
+    if (L == T && !(p >= k0 && p < k1)) return;  // wave-uniform
+    const int jl = j0 - (T - L);
+    const bool pin = p >= 0 && p < nz;
+#pragma unroll
+    for (int q = 0; q < S::nl(L); ++q) {
+        const int j = jl + q;
+        const double c = centre[S::off(L - 1) + q + 1];
+        const double left = from_left(c), right = from_right(c);
+        const double xm = (L == 1 && lane == 0) ? ex[q] : left;
+        const double xp = (L == 1 && lane == 63) ? ex[q] : right;
+        double v = xm + xp;
+        v = v + centre[S::off(L - 1) + q];
+        v = v + centre[S::off(L - 1) + q + 2];
+        v = v + below[S::offm(L - 1) + q];
+        v = v + fresh[S::off(L - 1) + q + 1];
+        if constexpr (L < T) {
+            fresh[S::off(L) + q] = (pin && xin && j >= 0 && j < ny) ? v * kSixth : 0.0;
+        } else {
+            if (lane_out && j < ny) put<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kSixth);
+        }
+    }
+    if constexpr (L < T)
+        tb_level<T, R, L + 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
+                                  lane, i, xin, lane_out);
+}
+
+// Shift every level by one plane: below <- centre (centre rows of the next
+// level), centre <- fresh.
+template <int T, int R, int L>
+__device__ __forceinline__ void tb_rotate(double* below, double* centre, const double* fresh) {
+    using S = TbShape<T, R>;
+#pragma unroll
+    for (int q = 0; q < S::nl(L + 1); ++q) below[S::offm(L) + q] = centre[S::off(L) + q + 1];
+#pragma unroll
+    for (int q = 0; q < S::nl(L); ++q) centre[S::off(L) + q] = fresh[S::off(L) + q];
+    if constexpr (L + 1 < T) tb_rotate<T, R, L + 1>(below, centre, fresh);
+}
+
+// T sweeps of src on the wave's column: lanes hold x = i0 + lane, output
+// rows j0 .. j0+R-1 (j0 < ny), output planes [k0, k1); level T is stored on
+// lanes lane_lo .. lane_hi that lie inside the grid (the caller keeps that
+// window within T-1 .. 64-T).  Every load is bounds-checked; the whole wave
+// must call this (cross-lane moves).
+template <int T, int R, bool NT>
+__device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
+                                          int nx, int ny, int nz, int i0, int j0, int k0, int k1,
+                                          int lane_lo, int lane_hi) {
+    using S = TbShape<T, R>;
+    const int lane = (int)(threadIdx.x & 63);
+    const int i = i0 + lane;
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const bool xin = i >= 0 && i < nx;
+    const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
+    const bool eok = (lane == 0 || lane == 63) && ie >= 0 && ie < nx;
+    const bool lane_out = lane >= lane_lo && lane <= lane_hi && xin;
+    auto ld = [&](int k, int j, int x, bool ok) -> double {
+        return (ok && k >= 0 && k < nz && j >= 0 && j < ny) ? src[(size_t)k * plane + (size_t)j * nx + x]
+                                                          : 0.0;
+    };
+    double below[S::kBelow], centre[S::kAll], fresh[S::kAll];
+    const int ka = k0 - T + 1;  // first iteration: level 1 at plane ka
+#pragma unroll
+    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, i, xin);
+#pragma unroll
+    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, i, xin);
+#pragma unroll
+    for (int q = S::nl(1); q < S::kBelow; ++q) below[q] = 0.0;
+#pragma unroll
+    for (int q = S::nl(0); q < S::kAll; ++q) centre[q] = 0.0;
+    for (int k = ka; k <= k1 + T - 2; ++k) {
+        double ex[S::nl(1)];
+#pragma unroll
+        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, i, xin);
+#pragma unroll
+        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, ie, eok);
+        tb_level<T, R, 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
+                              lane, i, xin, lane_out);
+        tb_rotate<T, R, 0>(below, centre, fresh);
+    }
+}
+
+}  // namespace zm
+}  // namespace ao

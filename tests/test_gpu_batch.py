@@ -88,3 +88,31 @@ def test_batch_256_uneven_graph_and_autotune(env):
         torch.cuda.synchronize()
         del junk
     ao.batch_destroy(b)
+
+
+def test_every_tile_candidate_bit_identical(env, orc):
+    # every tile of the autotuner's table (single-sweep and fused two-sweep)
+    # forced on every bucket: instances of all sizes, sweep counts 0..7
+    ao, torch, dev, st = env
+    shapes = [(8, 8, 8), (5, 17, 3), (70, 9, 40), (1, 1, 30), (33, 65, 2), (130, 20, 11),
+              (16, 16, 16), (3, 200, 4), (63, 62, 5), (125, 7, 64), (62, 1, 1), (124, 33, 9)]
+    sweeps = [5, 1, 4, 3, 0, 2, 7, 5, 6, 1, 3, 4]
+    ins, bufs = _instances(ao, torch, dev, shapes, sweeps, 1700)
+    refs = _reference(ao, torch, st, ins, bufs)
+    for q in (0, 1, 3, 10):   # standalone runs pinned to the oracle on small instances
+        nx, ny, nz = shapes[q]
+        want = orc.jacobi7(bufs[q][0].cpu().numpy(), nx, ny, nz, sweeps[q])
+        assert np.array_equal(refs[q].cpu().numpy(), want)
+    b = ao.batch_create(ins)
+    cands = ao.batch_candidates()
+    assert any(k > 10 for k, *_ in cands) and any(k == 0 for k, *_ in cands)
+    for c, tile in enumerate(cands):
+        ao.batch_set_tiles(b, [c] * 5)
+        assert all(t == tuple(tile[1:]) for t in ao.batch_info(b)[2])
+        for use_graph in (False, True):
+            for _, out in bufs:
+                out.fill_(float("nan"))
+            ao.batch_run(b, stream=st, use_graph=use_graph)
+            torch.cuda.synchronize()
+            _check(torch, bufs, refs, f"candidate {c} {tile} graph={use_graph}")
+    ao.batch_destroy(b)

@@ -188,3 +188,16 @@ def test_selector_select_untrained_returns_exploration_id(ao):
     rc, ids = ao.selector_select(h, [[1, 2, 3, 4, 5, 6]] * 3)
     assert rc == ao.AO_NOTE_UNTRAINED and ids == [0, 0, 0]
     ao.region_destroy(h)
+
+
+def test_batch_candidate_table_and_tile_errors(ao):
+    cands = ao.batch_candidates()
+    assert len(cands) == ao.lib.batch_candidates(None) >= 16
+    for kind, tx, ty, tz in cands:
+        assert kind in (0, 1, 2, 4, 11, 12, 14) and tz >= 1
+        if kind in (1, 2, 4):
+            assert (tx, ty) == (64, 4 * kind)
+        if kind > 10:
+            assert (tx, ty) == (62, 4 * (kind - 10))
+    with pytest.raises(ao.AdaptError):
+        ao.batch_set_tiles(None, [0] * 5)
