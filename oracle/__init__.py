@@ -19,7 +19,10 @@ Contents (paper section cited on each function):
     ``model_type`` and Sec. 4; every detail of it is a reading, see
     ``mlp_*``);
   * the paper's own model, a CART decision-tree classifier on
-    fastest-variant labels (``dtree_*``).
+    fastest-variant labels (``dtree_*``);
+  * the K-fold subset construction of the evaluation protocol (Sec. 4,
+    Adaptive-25/50/75) and the Online comparator's explore-then-exploit
+    choice (Sec. 4, GPU threads).
 """
 from __future__ import annotations
 
@@ -479,4 +482,43 @@ def dtree_predict(tree: dict, features, allowed=None) -> int:
     for k, c in enumerate(node["counts"]):
         if (allowed is None or k in allowed) and c > 0 and (best < 0 or c > node["counts"][best]):
             best = k
+    return best
+
+
+# --------------------------------------------------------------------------
+# Evaluation protocol (Sec. 4, CPU-GPU execution): inputs are split into K
+# equal groups, a fraction of the groups trains and the rest tests, each
+# input trained on and tested at least once, the split redrawn from a
+# shuffled order.  Reading: reshuffle r orders the inputs by SplitMix64
+# keys of substream(seed, 40 + r) (ties by index), group g takes the order's
+# positions [g*Q//K, (g+1)*Q//K), and m training groups rotate as groups
+# t, t+1, ..., t+m-1 (mod K) for t = 0..K-1.
+# --------------------------------------------------------------------------
+
+def kfold_groups(count: int, k: int, seed: int, reshuffle: int) -> list:
+    import synth
+    keys = [int(v) for v in synth.splitmix64(synth.substream(seed, 40 + reshuffle), count)]
+    order = [i for _, i in sorted((keys[i], i) for i in range(count))]
+    groups = []
+    for g in range(k):
+        lo, hi = g * count // k, (g + 1) * count // k
+        groups.append(order[lo:hi])
+    return groups
+
+
+def rotations(k: int, m: int) -> list:
+    out = []
+    for t in range(k):
+        out.append(sorted((t + d) % k for d in range(m)))
+    return out
+
+
+def online_choice(explored_seconds) -> int:
+    """Online comparator (Sec. 4, GPU threads): after one exploration run of
+    every variant on a single input, a model trained on those samples picks
+    the fastest measured variant (ties to the lowest id)."""
+    best = 0
+    for v in range(1, len(explored_seconds)):
+        if explored_seconds[v] < explored_seconds[best]:
+            best = v
     return best
