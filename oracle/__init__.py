@@ -7,7 +7,8 @@ and its Python binding never do, and the two share no code.
 
 Contents (paper section cited on each function):
   * region arithmetic (serial C, ``oracle.c``): 7-point Jacobi, CSR SpMV in
-    plain and in canonical pairwise order;
+    plain and in canonical pairwise order, weighted Jacobi relaxation on the
+    canonical SpMV;
   * region features (Sec. 3.1 ``features`` clause);
   * numeric variant ranges (Sec. 3.1 ``variants`` clause);
   * RoundRobin exploration and the train trigger (Sec. 2, Apollo paragraph;
@@ -52,14 +53,16 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=False)
+        src = os.path.join(_HERE, "oracle.c")
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+            build(force=True)
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         lib.orc_jacobi7.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.orc_spmv_plain.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.orc_spmv_canonical.argtypes = [ctypes.c_int, P, P, P, P, P]
-        for f in (lib.orc_jacobi7, lib.orc_spmv_plain, lib.orc_spmv_canonical):
+        lib.orc_relax.argtypes = [ctypes.c_int, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int, P]
+        for f in (lib.orc_jacobi7, lib.orc_spmv_plain, lib.orc_spmv_canonical, lib.orc_relax):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -115,6 +118,28 @@ def spmv_canonical(row_ptr, col, val, x) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"orc_spmv_canonical failed ({rc})")
     return y
+
+
+def relax(row_ptr, col, val, x, b, d, omega: float, sweeps: int) -> np.ndarray:
+    """Weighted Jacobi relaxation x <- x + (omega * (b - A x)) / d, `sweeps`
+    times (the AMGMk relax kernel, Table 3); A x in the canonical order, the
+    update rounded step by step (subtract, multiply, divide, add)."""
+    row_ptr, col, val, x = _csr_args(row_ptr, col, val, x)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    n = row_ptr.size - 1
+    y = np.empty(n, dtype=np.float64)
+    rc = _load().orc_relax(n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(b), _ptr(d),
+                           float(omega), int(sweeps), _ptr(y))
+    if rc != 0:
+        raise RuntimeError(f"orc_relax failed ({rc})")
+    return y
+
+
+def relax_bytes(n: int, nnz: int) -> int:
+    """Algorithmic bytes of one relaxation sweep: the SpMV's (matrix once,
+    x once, the new x once) plus b and d once."""
+    return spmv_bytes(n, nnz) + 16 * n
 
 
 def jacobi_bytes(nx: int, ny: int, nz: int, sweeps: int) -> int:

@@ -115,3 +115,33 @@ int orc_spmv_canonical(int n, const int32_t* row_ptr, const int32_t* col, const 
     free(s);
     return 0;
 }
+
+/* Weighted Jacobi relaxation (the AMGMk relax kernel of Table 3):
+ * `sweeps` applications of x <- x + (omega * (b - A x)) / d, each row sum of
+ * A x in the canonical order above, then one subtraction, one
+ * multiplication, one division and one addition, each rounded (no FMA).
+ * x is read, the last sweep lands in y; d holds the diagonal of A. */
+int orc_relax(int n, const int32_t* row_ptr, const int32_t* col, const double* val,
+              const double* x, const double* b, const double* d, double omega, int sweeps,
+              double* y)
+{
+    if (n < 0 || sweeps < 0) return -1;
+    double* cur = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double* ax = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!cur || !ax) { free(cur); free(ax); return -2; }
+    memcpy(cur, x, (size_t)n * sizeof(double));
+    for (int s = 0; s < sweeps; ++s) {
+        int rc = orc_spmv_canonical(n, row_ptr, col, val, cur, ax);
+        if (rc != 0) { free(cur); free(ax); return rc; }
+        for (int i = 0; i < n; ++i) {
+            double r = b[i] - ax[i];
+            double t = omega * r;
+            double u = t / d[i];
+            cur[i] = cur[i] + u;
+        }
+    }
+    memcpy(y, cur, (size_t)n * sizeof(double));
+    free(cur);
+    free(ax);
+    return 0;
+}

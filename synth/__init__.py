@@ -185,6 +185,35 @@ def csr_matrix(n: int, seed: int, mean: float = 16.0, tail: float = 1.5, max_len
     return {"row_ptr": row_ptr, "col": col, "val": val, "x": x}
 
 
+def relax_system(n: int, seed: int, mean: float = 16.0, tail: float = 1.5, max_len: int = 4096):
+    """A linear system for the weighted-Jacobi relaxation workload: the
+    csr_matrix(n, seed) off-diagonal pattern and values (an entry that falls
+    on the diagonal is dropped) plus a diagonal entry in every row, d_i = 1 +
+    sum_j |a_ij| over the row's off-diagonal entries (strict diagonal
+    dominance), stored in column order; b ~ U[-1,1) and a starting vector
+    x ~ U[-1,1) from their own substreams.
+
+    Returns dict(row_ptr, col, val, d f64[n], b f64[n], x f64[n])."""
+    m = csr_matrix(n, seed, mean=mean, tail=tail, max_len=max_len)
+    row_ptr, col, val = m["row_ptr"], m["col"], m["val"]
+    lengths = np.diff(row_ptr.astype(np.int64))
+    rows = np.repeat(np.arange(n, dtype=np.int64), lengths)
+    keep = col.astype(np.int64) != rows
+    rows, col, val = rows[keep], col[keep], val[keep]
+    kept = np.bincount(rows, minlength=n)
+    d = 1.0 + np.bincount(rows, weights=np.abs(val), minlength=n)
+    keys = rows * n + col.astype(np.int64)
+    diag = np.arange(n, dtype=np.int64)
+    at = np.searchsorted(keys, diag * n + diag)
+    col = np.insert(col, at, diag.astype(np.int32))
+    val = np.insert(val, at, d)
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum(kept + 1).astype(np.int32)
+    b = 2.0 * u01(substream(seed, 6), n) - 1.0
+    x = 2.0 * u01(substream(seed, 7), n) - 1.0
+    return {"row_ptr": row_ptr, "col": col.astype(np.int32), "val": val, "d": d, "b": b, "x": x}
+
+
 # --------------------------------------------------------------------------
 # The same streams drawn on a torch device (int64 two's-complement wrap
 # equals the uint64 arithmetic above; right shifts are made logical).
