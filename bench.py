@@ -271,6 +271,97 @@ def spmv_workload(steps: int, warmup: int):
     print(json.dumps(res), flush=True)
 
 
+def relax_workload(steps: int, warmup: int):
+    """Weighted Jacobi relaxation region (the AMGMk relax kernel): n = 2^22
+    rows of the Pareto-row matrix (tail 1.5, mean 16, max 4096, seed 5) with
+    a strictly dominant diagonal, omega = 2/3, 10 sweeps per execution; the
+    9 SpMV variants with the update fused into each row's store.  The cost
+    model is trained on profiled systems of other sizes, row laws and sweep
+    counts (n 2^14..2^20, seeds 70+), then chooses on held-out systems (2^21
+    and the 2^22 target); regret against their exhaustive tables.  Bytes per
+    sweep: the SpMV's (12 nnz + 4(n+1) + 8n x + 8n new x) plus b and diag
+    (16n).  Prints one JSON line."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    V = 9
+    omega, S = 2.0 / 3.0, 10
+    region = ao.region_declare_variants("bench_relax", ao.AO_CSR_RELAX_F64, ao.spmv_variants(),
+                                        min_train_data=10 ** 9, model_type="mlp")
+
+    def load(n, seed, tail, mean, sweeps):
+        m = synth.relax_system(n, seed, mean=mean, tail=tail, max_len=4096)
+        t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        nnz = int(m["col"].size)
+        a = ao.relax_args(t["row_ptr"], t["col"], t["val"], t["x"], y, t["b"], t["d"], omega,
+                          sweeps, n, nnz)
+        return t, y, a, nnz
+
+    t0 = time.perf_counter()
+    seed = 70
+    for lg in (14, 16, 18, 20):
+        for tail in (1.2, 1.5, 2.0, 3.0):
+            for mean, sweeps in ((4.0, 2), (16.0, 10), (64.0, 5)):
+                t, y, a, _ = load(1 << lg, seed, tail, mean, sweeps)
+                ao.region_profile(region, a, warmup=1, reps=3, stream=stream, record=True,
+                                  num_variants=V)
+                seed += 1
+                del t, y
+        _log(f"relax training systems up to 2^{lg}: {time.perf_counter() - t0:.0f} s")
+    train_s = time.perf_counter() - t0
+    loss = ao.selector_train(region, epochs=400, batch=64, lr=3e-3, seed=7)
+    _log(f"relax selector: {seed - 70} training systems in {train_s:.0f} s, loss {loss:.4g}")
+
+    held = [(1 << 21, 700 + q, tail, mean) for q, (tail, mean) in
+            enumerate([(1.2, 16.0), (1.5, 4.0), (2.0, 64.0), (3.0, 16.0)])]
+    held.append((1 << 22, 5, 1.5, 16.0))
+    regrets, rows = [], []
+    for n, sd, tail, mean in held:
+        t, y, a, nnz = load(n, sd, tail, mean, S)
+        med = ao.region_profile(region, a, warmup=1, reps=5, stream=stream, num_variants=V)
+        _, ids = ao.selector_select(region, [ao.region_features(region, a, stream=stream)])
+        chosen = ids[0]
+        best = min(range(V), key=lambda v: med[v])
+        regrets.append(med[chosen] / med[best] - 1.0)
+        byt = S * (12 * nnz + 4 * (n + 1) + 32 * n)
+        rows.append({"n": n, "seed": sd, "tail": tail, "mean": mean, "nnz": nnz,
+                     "chosen": chosen, "best": best, "regret_pct": round(100 * regrets[-1], 3),
+                     "gbs": [round(byt / x / 1e9, 1) for x in med]})
+        _log(f"held-out relax n={n} seed={sd}: chosen {chosen}, best {best}")
+        if n == 1 << 22:
+            target = (t, y, a, nnz, chosen, med, byt)
+        else:
+            del t, y
+    t, y, a, nnz, chosen, med, byt = target
+    for _ in range(warmup):
+        ao.region_run(region, a, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ao.region_run(region, a, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / steps * 1e-3
+    r = np.asarray(regrets) + 1.0
+    res = {"metric": "relaxation region GB/s (learned selection); selector regret %",
+           "value": round(byt / sec / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "weighted Jacobi relaxation, omega 2/3, 10 sweeps, n=2^22 "
+                                  "Pareto rows tail 1.5 mean 16 max 4096 + dominant diagonal, seed 5",
+                      "nnz": nnz, "algorithmic_bytes": byt},
+           "pct_hbm_peak": round(100.0 * byt / sec / 1e9 / HBM_PEAK_GBS, 2),
+           "chosen_variant": chosen, "ms_per_execution": round(sec * 1e3, 3),
+           "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
+           "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
+           "held_out": rows}
+    print(json.dumps(res), flush=True)
+
+
 def spmv_kernel_only(variant: int, launches: int = 5):
     """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
     executions."""
@@ -302,8 +393,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=None,
                     help="counter-collection mode: run one size-sweep variant at 512^3 only")
-    ap.add_argument("--workload", default="size-sweep", choices=["size-sweep", "batch", "spmv"],
-                    help="size-sweep: the headline line; batch / spmv: the other region lines")
+    ap.add_argument("--workload", default="size-sweep",
+                    choices=["size-sweep", "batch", "spmv", "relax"],
+                    help="size-sweep: the headline line; batch / spmv / relax: the other region lines")
     args = ap.parse_args()
     if args.kernel_only is not None:
         if args.workload == "spmv":
@@ -316,6 +408,9 @@ def main():
         return
     if args.workload == "spmv":
         spmv_workload(args.steps, args.warmup)
+        return
+    if args.workload == "relax":
+        relax_workload(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "

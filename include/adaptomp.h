@@ -67,7 +67,16 @@ enum ao_kind {
      * fl(val*x[col]) indexed by their position in the row, padded with -0.0
      * to a power of two and added pairwise level by level (an empty row
      * gives +0.0).  (Sparse workload: AMGMk relax, Table 3.) */
-    AO_CSR_SPMV_F64 = 1
+    AO_CSR_SPMV_F64 = 1,
+    /* Weighted Jacobi relaxation, the AMGMk relax kernel (Table 3): S =
+     * sweeps applications of x <- x + (omega * (b - A x)) / diag, A x as in
+     * AO_CSR_SPMV_F64 (canonical order), then one subtraction,
+     * multiplication, division and addition per row, each rounded (no FMA).
+     * x (the starting vector) is read, the S-th sweep lands in y; S = 0
+     * copies x.  diag[n] is A's diagonal (the caller's; the library does not
+     * look it up).  y must not overlap x, b, diag or the matrix arrays.
+     * Uses the SpMV variant families; device-resident only. */
+    AO_CSR_RELAX_F64 = 2
 };
 
 enum ao_target { AO_TARGET_GPU = 0, AO_TARGET_HOST = 1 };
@@ -132,6 +141,11 @@ typedef struct ao_args {
      * buffer, an edited matrix).  0 = unknown: the plan is rebuilt on every
      * call. */
     uint64_t structure_id;
+    /* Relaxation (AO_CSR_RELAX_F64; x, y, the matrix and sweeps as above):
+     * right-hand side b[n], diagonal diag[n], weight omega. */
+    const double* b;
+    const double* diag;
+    double omega;
 } ao_args;
 
 typedef struct ao_region ao_region; /* opaque, library-owned */
@@ -162,7 +176,8 @@ int region_declare_variants(const char* model_name, int kind, const ao_variant* 
  *             [log2 nx, log2 ny, log2 nz, sweeps, log2(16*N*sweeps),
  *             resident]; SpMV [log2 n, log2 nnz, mean row length,
  *             log2(1 + row-length variance), log2 max row length] (computed
- *             once per matrix on the GPU and cached).
+ *             once per matrix on the GPU and cached); relaxation: the SpMV
+ *             features and sweeps.
  *   variant   -1: the producer decides (RoundRobin before training, the
  *             model's argmin after, exhaustive timing for
  *             model_type "exhaustive"); >= 0: run that id.

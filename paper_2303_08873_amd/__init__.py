@@ -10,7 +10,7 @@ has not been built: there is no fallback path.
 from __future__ import annotations
 
 from ._lib import (  # noqa: F401
-    AO_CSR_SPMV_F64, AO_JACOBI7_F64, AO_MAX_FEATURES, AO_MAX_VARIANTS, AO_MLP_PARAMS,
+    AO_CSR_RELAX_F64, AO_CSR_SPMV_F64, AO_JACOBI7_F64, AO_MAX_FEATURES, AO_MAX_VARIANTS, AO_MLP_PARAMS,
     AO_OK, AO_NOTE_FALLBACK, AO_NOTE_UNTRAINED, AO_PROFILE_RECORD, AO_TARGET_GPU,
     AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_OCCUPANCY, FAM_JACOBI_DIRECT,
     FAM_JACOBI_HOST, FAM_JACOBI_ZMARCH, FAM_JACOBI_ZREG, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
@@ -21,6 +21,6 @@ from ._lib import (  # noqa: F401
     batch_run, batch_set_tiles,
     region_clear_memo, region_declare_variants, region_destroy, region_features, region_load, region_profile,
     region_record, region_records, region_run, region_save, region_stats, selector_select, selector_train,
-    jacobi_args, spmv_args)
+    jacobi_args, relax_args, spmv_args)
 from .variants import (  # noqa: F401
     jacobi_variants_blocks, jacobi_variants_sweep, spmv_variants)

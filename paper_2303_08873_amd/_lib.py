@@ -11,7 +11,7 @@ lib_path = os.path.join(_HERE, "libadaptomp.so")
 
 AO_OK, AO_NOTE_UNTRAINED, AO_NOTE_FALLBACK = 0, 1, 2
 AO_MAX_VARIANTS, AO_MAX_FEATURES, AO_MLP_PARAMS = 12, 6, 5388
-AO_JACOBI7_F64, AO_CSR_SPMV_F64 = 0, 1
+AO_JACOBI7_F64, AO_CSR_SPMV_F64, AO_CSR_RELAX_F64 = 0, 1, 2
 AO_TARGET_GPU, AO_TARGET_HOST = 0, 1
 FAM_JACOBI_DIRECT, FAM_JACOBI_ZMARCH, FAM_JACOBI_HOST, FAM_JACOBI_ZREG = 0, 1, 2, 3
 FAM_JACOBI_ZREG_T2 = 4
@@ -50,7 +50,8 @@ class Args(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
-                ("structure_id", ctypes.c_uint64)]
+                ("structure_id", ctypes.c_uint64),
+                ("b", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("omega", ctypes.c_double)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -334,4 +335,15 @@ def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int, structure_id: int | Non
     a.resident = 1
     a.row_ptr, a.col, a.val, a.x, a.y = _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y)
     a.n, a.nnz = n, nnz
+    return a
+
+
+def relax_args(row_ptr, col, val, x, y, b, diag, omega: float, sweeps: int, n: int, nnz: int,
+               structure_id: int | None = None) -> Args:
+    """Arguments of one weighted-Jacobi relaxation execution (S sweeps of
+    x <- x + omega (b - A x) / diag from x into y); structure ids as for
+    spmv_args."""
+    a = spmv_args(row_ptr, col, val, x, y, n, nnz, structure_id)
+    a.kind = AO_CSR_RELAX_F64
+    a.b, a.diag, a.omega, a.sweeps = _ptr(b), _ptr(diag), float(omega), int(sweeps)
     return a

@@ -60,8 +60,15 @@ struct SpmvPlan {
 hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s);
 
 hipError_t spmv_features(SpmvPlan& p, hipStream_t s);
+// What a finished row i with canonical sum s_i stores: y_i = s_i (b ==
+// NULL), or the relaxation update y_i = x_i + (omega * (b_i - s_i)) / d_i.
+struct SpmvEpi {
+    const double* b = nullptr;
+    const double* d = nullptr;
+    double omega = 0.0;
+};
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                    const double* x, double* y, hipStream_t s);
+                    const double* x, double* y, hipStream_t s, const SpmvEpi& ep = SpmvEpi());
 
 // Cost model kernels.
 struct MlpNorm {

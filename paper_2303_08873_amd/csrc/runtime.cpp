@@ -201,7 +201,7 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             return fail(AO_EINVAL, at + "z-march needs bz > 0");
         return AO_OK;
     }
-    if (kind == AO_CSR_SPMV_F64) {
+    if (kind == AO_CSR_SPMV_F64 || kind == AO_CSR_RELAX_F64) {
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "SpMV variants run on the GPU");
         if (v.family != AO_FAM_SPMV_THREAD_ROW && v.family != AO_FAM_SPMV_WAVE_ROW &&
             v.family != AO_FAM_SPMV_MERGE_PATH)
@@ -239,6 +239,24 @@ int validate_args(const ao_region* r, const ao_args* a) {
     if (a->n > 0 && (!a->row_ptr || !a->x || !a->y))
         return fail(AO_EINVAL, "row_ptr/x/y is NULL");
     if (a->nnz > 0 && (!a->col || !a->val)) return fail(AO_EINVAL, "col/val is NULL");
+    if (r->kind == AO_CSR_RELAX_F64) {
+        if (a->sweeps < 0) return fail(AO_EINVAL, "negative sweep count");
+        if (!isfinite(a->omega)) return fail(AO_EINVAL, "omega must be finite");
+        if (a->n > 0 && (!a->b || !a->diag)) return fail(AO_EINVAL, "b/diag is NULL");
+        // y is written while x (every column), b, diag and the matrix are read
+        auto overlaps = [&](const void* p, size_t bytes) {
+            const char* q = (const char*)p;
+            const char* yy = (const char*)a->y;
+            const size_t yb = (size_t)a->n * 8;
+            return p && bytes > 0 && q < yy + yb && yy < q + bytes;
+        };
+        const size_t nb = (size_t)a->n * 8;
+        if (a->n > 0 && (overlaps(a->x, nb) || overlaps(a->b, nb) || overlaps(a->diag, nb) ||
+                         overlaps(a->val, (size_t)a->nnz * 8) ||
+                         overlaps(a->col, (size_t)a->nnz * 4) ||
+                         overlaps(a->row_ptr, ((size_t)a->n + 1) * 4)))
+            return fail(AO_EINVAL, "y overlaps an input of the relaxation");
+    }
     return AO_OK;
 }
 
@@ -369,6 +387,7 @@ int compute_features(ao_region* r, const ao_args* a, hipStream_t s, float* f) {
     SpmvPlan* p = get_plan(r, a, s, &rc);
     if (!p) return rc;
     memcpy(f, p->features, sizeof(p->features));
+    if (r->kind == AO_CSR_RELAX_F64) f[5] = (float)a->sweeps;
     return AO_OK;
 }
 
@@ -514,7 +533,34 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
     hipEvent_t e0 = get_event(r), e1 = get_event(r);
     if (!e0 || !e1) return fail(AO_EHIP, "event creation failed");
     hipError_t e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = spmv_gpu(v, *p, a->col, a->val, a->x, a->y, s);
+    if (r->kind == AO_CSR_SPMV_F64) {
+        if (e == hipSuccess) e = spmv_gpu(v, *p, a->col, a->val, a->x, a->y, s);
+    } else {
+        // relaxation: S sweeps ping-ponging between y and the region's
+        // scratch so that the last one lands in y
+        const int S = a->sweeps;
+        const size_t n = (size_t)std::max(a->n, 0);
+        if (S > 1) {
+            const int rc2 = ensure_dev(r, std::max<size_t>(n, 1));
+            if (rc2) {
+                r->pool.push_back(e0);
+                r->pool.push_back(e1);
+                return rc2;
+            }
+        }
+        SpmvEpi ep;
+        ep.b = a->b;
+        ep.d = a->diag;
+        ep.omega = a->omega;
+        if (S == 0 && n > 0 && e == hipSuccess)
+            e = hipMemcpyAsync(a->y, a->x, n * 8, hipMemcpyDeviceToDevice, s);
+        const double* src = a->x;
+        for (int k = 0; k < S && e == hipSuccess; ++k) {
+            double* dst = ((S - 1 - k) % 2 == 0) ? a->y : r->d_a;
+            e = spmv_gpu(v, *p, a->col, a->val, src, dst, s, ep);
+            src = dst;
+        }
+    }
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e != hipSuccess) {
         r->pool.push_back(e0);
@@ -1021,7 +1067,7 @@ int region_declare_variants(const char* model_name, int kind, const ao_variant* 
                             ao_region** out) {
     if (!model_name || !*model_name) return fail(AO_EINVAL, "model_name is required");
     if (!out) return fail(AO_EINVAL, "out is NULL");
-    if (kind != AO_JACOBI7_F64 && kind != AO_CSR_SPMV_F64)
+    if (kind != AO_JACOBI7_F64 && kind != AO_CSR_SPMV_F64 && kind != AO_CSR_RELAX_F64)
         return fail(AO_EINVAL, "unknown region kind");
     if (!variants || num_variants < 1 || num_variants > AO_MAX_VARIANTS)
         return fail(AO_EINVAL, "need 1..12 variants");

@@ -65,11 +65,22 @@ __device__ __forceinline__ double prod(const int32_t* __restrict__ col,
     return val[k] * x[col[k]];
 }
 
+// The value stored for finished row i: the canonical sum, or the
+// relaxation update x_i + (omega * (b_i - s)) / d_i rounded step by step.
+__device__ __forceinline__ double row_out(const SpmvEpi& ep, const double* __restrict__ x, int i,
+                                          double s) {
+    if (ep.b == nullptr) return s;
+    const double r = ep.b[i] - s;
+    const double t = ep.omega * r;
+    const double u = t / ep.d[i];
+    return x[i] + u;
+}
+
 __global__ __launch_bounds__(1024) void k_thread_row(int n, const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ val,
                                                      const double* __restrict__ x,
-                                                     double* __restrict__ y) {
+                                                     double* __restrict__ y, SpmvEpi ep) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
     const int32_t b = row_ptr[i], e = row_ptr[i + 1];
@@ -82,7 +93,7 @@ __global__ __launch_bounds__(1024) void k_thread_row(int n, const int32_t* __res
         const double s03 = s01 + s23, s47 = s45 + s67;
         c.push(s03 + s47);
     }
-    y[i] = c.finish();
+    y[i] = row_out(ep, x, i, c.finish());
 }
 
 template <int W>
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(1024) void k_wave_row(int n, const int32_t* __restr
                                                    const int32_t* __restrict__ col,
                                                    const double* __restrict__ val,
                                                    const double* __restrict__ x,
-                                                   double* __restrict__ y) {
+                                                   double* __restrict__ y, SpmvEpi ep) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i64 = gid / W;
     const int g = (int)(threadIdx.x % W);
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(1024) void k_wave_row(int n, const int32_t* __restr
         for (int off = 1; off < W; off <<= 1) v = v + __shfl_xor(v, off);
         if (t * W < e - b) c.push(v);
     }
-    if (live && g == 0) y[i] = c.finish();
+    if (live && g == 0) y[i] = row_out(ep, x, i, c.finish());
 }
 
 // ---- features: one pass over row_ptr, deterministic two-level reduction ----
@@ -205,17 +216,18 @@ hipError_t spmv_features(SpmvPlan& p, hipStream_t s) {
 }
 
 hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                           const double* x, double* y, hipStream_t s);
+                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep);
 
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                    const double* x, double* y, hipStream_t s) {
+                    const double* x, double* y, hipStream_t s, const SpmvEpi& ep) {
     if (p.n <= 0) return hipSuccess;
     const int B = v.bx;
     if (B <= 0 || B > 1024 || B % 64 != 0) return hipErrorInvalidConfiguration;
     if (v.family == AO_FAM_SPMV_THREAD_ROW) {
         if ((int64_t)p.max_len > ((int64_t)8 << kCounterLevels)) return hipErrorInvalidConfiguration;
         const unsigned grid = (unsigned)(((int64_t)p.n + B - 1) / B);
-        hipLaunchKernelGGL(k_thread_row, dim3(grid), dim3(B), 0, s, p.n, p.row_ptr, col, val, x, y);
+        hipLaunchKernelGGL(k_thread_row, dim3(grid), dim3(B), 0, s, p.n, p.row_ptr, col, val, x, y,
+                           ep);
         return hipGetLastError();
     }
     if (v.family == AO_FAM_SPMV_WAVE_ROW) {
@@ -228,7 +240,7 @@ hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const 
 #define AO_WR(WW)                                                                                  \
     case WW:                                                                                       \
         hipLaunchKernelGGL(k_wave_row<WW>, dim3((unsigned)grid), dim3(B), 0, s, p.n, p.row_ptr, \
-                           col, val, x, y);                                                        \
+                           col, val, x, y, ep);                                                    \
         break;
             AO_WR(1) AO_WR(2) AO_WR(4) AO_WR(8) AO_WR(16) AO_WR(32) AO_WR(64)
 #undef AO_WR
@@ -237,7 +249,7 @@ hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const 
         }
         return hipGetLastError();
     }
-    if (v.family == AO_FAM_SPMV_MERGE_PATH) return spmv_merge_path(v, p, col, val, x, y, s);
+    if (v.family == AO_FAM_SPMV_MERGE_PATH) return spmv_merge_path(v, p, col, val, x, y, s, ep);
     return hipErrorInvalidValue;
 }
 
@@ -360,7 +372,8 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
                                                   const int32_t* __restrict__ srow,
                                                   const int32_t* __restrict__ sunit,
                                                   const int32_t* __restrict__ unit_ptr,
-                                                  double* __restrict__ unit_sums, int64_t units) {
+                                                  double* __restrict__ unit_sums, int64_t units,
+                                                  SpmvEpi ep) {
     constexpr int D = 4 * B;
     // a unit that starts just below the block's cost limit may extend 64
     // leaves past it: at most D + 64 leaves and D rows per block
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
                 const int32_t o = g - e0;
                 if (g < re && o >= 0 && o < cnt) c.push(s[o]);
             }
-            y[i] = c.finish();
+            y[i] = row_out(ep, x, i, c.finish());
         } else {
             for (int32_t j = ja; j < jb; ++j) {
                 const int32_t g = rb + 64 * j;
@@ -450,7 +463,7 @@ __global__ void k_merge_fixup(int n, int nb, const int32_t* __restrict__ row_ptr
                               const int32_t* __restrict__ srow, const int32_t* __restrict__ sunit,
                               const int32_t* __restrict__ unit_ptr,
                               const double* __restrict__ unit_sums, int64_t units,
-                              double* __restrict__ y) {
+                              const double* __restrict__ x, double* __restrict__ y, SpmvEpi ep) {
     const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (b <= 0 || b >= nb) return;
     if (sunit[b] == 0) return;
@@ -464,7 +477,7 @@ __global__ void k_merge_fixup(int n, int nb, const int32_t* __restrict__ row_ptr
         const int64_t u = (int64_t)unit_ptr[i] + j;
         c.push((u >= 0 && u < units) ? unit_sums[u] : 0.0);
     }
-    y[i] = c.finish();
+    y[i] = row_out(ep, x, i, c.finish());
 }
 
 }  // namespace
@@ -520,7 +533,7 @@ hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s) {
 }
 
 hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                           const double* x, double* y, hipStream_t s) {
+                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep) {
     const int B = v.bx;
     const SpmvPlan::MergeSplit* m = nullptr;
     for (const auto& q : p.mp)
@@ -531,7 +544,7 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
     case BB:                                                                                \
         hipLaunchKernelGGL(k_merge_path<BB>, dim3(m->blocks), dim3(BB), 0, s, p.n, p.row_ptr, \
                            col, val, x, y, m->srow, m->sunit, p.unit_ptr, p.unit_sums,      \
-                           p.units);                                                        \
+                           p.units, ep);                                                    \
         break;
         AO_MP(64) AO_MP(128) AO_MP(256) AO_MP(512) AO_MP(1024)
 #undef AO_MP
@@ -542,7 +555,7 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_fixup, dim3((m->blocks + 255) / 256), dim3(256), 0, s, p.n,
                        m->blocks, p.row_ptr, m->srow, m->sunit, p.unit_ptr, p.unit_sums, p.units,
-                       y);
+                       x, y, ep);
     return hipGetLastError();
 }
 

@@ -201,3 +201,59 @@ def test_batch_candidate_table_and_tile_errors(ao):
             assert (tx, ty) == (62, 4 * (kind - 10))
     with pytest.raises(ao.AdaptError):
         ao.batch_set_tiles(None, [0] * 5)
+
+
+def test_args_and_variant_layout_match_the_header(ao, tmp_path):
+    # the ctypes mirrors of ao_args / ao_variant / ao_train_opts / ao_stats
+    # must match the C layout field by field
+    import ctypes
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"ao_args": ao.Args, "ao_variant": ao.Variant, "ao_train_opts": ao.TrainOpts,
+               "ao_stats": ao.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "adaptomp.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_relax_argument_errors(ao):
+    # argument checks run before any device work
+    import numpy as np
+    vs = ao.spmv_variants(blocks=(256,))
+    h = ao.region_declare_variants("relax_args_cpu", ao.AO_CSR_RELAX_F64, vs)
+    n = 16
+    rp = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    val = np.ones(n)
+    x, y, b, d = np.zeros(n), np.zeros(n), np.ones(n), np.ones(n)
+    bad = [ao.relax_args(rp, col, val, x, x, b, d, 1.0, 2, n, n),        # y is x
+           ao.relax_args(rp, col, val, x, y, None, d, 1.0, 2, n, n),     # no b
+           ao.relax_args(rp, col, val, x, y, b, None, 1.0, 2, n, n),     # no diag
+           ao.relax_args(rp, col, val, x, y, b, d, float("inf"), 2, n, n),
+           ao.relax_args(rp, col, val, x, y, b, d, 1.0, -1, n, n),
+           ao.relax_args(rp, col, val, x, b, b, d, 1.0, 2, n, n)]       # y is b
+    host = ao.relax_args(rp, col, val, x, y, b, d, 1.0, 2, n, n)
+    host.resident = 0                                                  # device only
+    bad.append(host)
+    for a in bad:
+        with pytest.raises(ao.AdaptError) as e:
+            ao.region_run(h, a, variant=0)
+        assert e.value.code == -1
+    ao.region_destroy(h)
+    with pytest.raises(ao.AdaptError):   # relaxation variants run on the GPU
+        ao.region_declare_variants("relax_host", ao.AO_CSR_RELAX_F64,
+                                   [ao.jacobi_variants_sweep()[5]])
