@@ -362,6 +362,83 @@ def relax_workload(steps: int, warmup: int):
     print(json.dumps(res), flush=True)
 
 
+def cosched_workload(steps: int, warmup: int):
+    """CPU+GPU co-scheduling of the Jacobi region (the paper's co-scheduling
+    use case): 11 variants giving the host 0.0, 0.1, ..., 1.0 of the
+    z-planes.  Cases: cubic n in {128, 192, ..., 512} x sweeps {1, 2, 4} x
+    data in device memory or in pinned host memory (u0 ~ U[0,1), seed 4242).
+    Every case is timed for every fraction (warmup 1, median of 3); the MLP
+    is trained on the cases of n = 128, 256, 384, 512 and picks the fraction
+    for n = 192, 320, 448.  Prints one JSON line: geomean speedup of the learned pick over the
+    better single target (all-GPU or all-host) on the held-out cases."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    V = 11
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_COSCHED, f, 0, 0, 0) for f in range(V)]
+    judge = ao.region_declare_variants("bench_cosched_table", ao.AO_JACOBI7_F64, vs,
+                                       min_train_data=10 ** 9, model_type="exhaustive")
+    nmax = 512 ** 3
+    u0_d = synth.u01_torch(4242, nmax, dev)
+    out_d = torch.empty_like(u0_d)
+    u0_h = torch.empty(nmax, dtype=torch.float64).pin_memory()
+    u0_h.copy_(u0_d)
+    out_h = torch.empty(nmax, dtype=torch.float64).pin_memory()
+    torch.cuda.synchronize()
+    cases = [(n, S, res) for n in (128, 192, 256, 320, 384, 448, 512) for S in (1, 2, 4)
+             for res in (0, 1)]
+    table, feats = [], []
+    t0 = time.perf_counter()
+    for q, (n, S, res) in enumerate(cases):
+        a = (ao.jacobi_args(u0_d, out_d, n, n, n, S, 1) if res else
+             ao.jacobi_args(u0_h, out_h, n, n, n, S, 0))
+        med = ao.region_profile(judge, a, warmup=1, reps=3, stream=stream, num_variants=V)
+        table.append(med)
+        feats.append(ao.region_features(judge, a))
+        _log(f"cosched n={n} S={S} resident={res}: best fraction "
+             f"{int(np.argmin(med)) / 10:.1f} " + " ".join(f"{t * 1e3:.2f}" for t in med) + " ms")
+    table = np.array(table)
+    table_s = time.perf_counter() - t0
+    ao.region_destroy(judge)
+    region = ao.region_declare_variants("bench_cosched", ao.AO_JACOBI7_F64, vs,
+                                        min_train_data=10 ** 9, model_type="mlp")
+    # held out: whole grid sizes (192, 320, 448), every sweep count and residency
+    train = [q for q, c in enumerate(cases) if c[0] in (128, 256, 384, 512)]
+    test = [q for q, c in enumerate(cases) if c[0] not in (128, 256, 384, 512)]
+    for q in train:
+        for v in range(V):
+            ao.region_record(region, feats[q], v, float(table[q, v]))
+    loss = ao.selector_train(region, epochs=400, batch=64, lr=3e-3, seed=7)
+    _, ids = ao.selector_select(region, [feats[q] for q in test])
+    ao.region_destroy(region)
+    best = table.min(axis=1)
+    pure = np.minimum(table[:, 0], table[:, V - 1])
+    sel = np.array([table[q, v] for q, v in zip(test, ids)])
+    geo = lambda x: float(np.exp(np.mean(np.log(x))))
+    rows = [{"n": n, "sweeps": S, "resident": res, "best_fraction": int(np.argmin(table[q])) / 10,
+             "ms": [round(t * 1e3, 3) for t in table[q]],
+             "speedup_best_over_better_single": round(float(pure[q] / best[q]), 3)}
+            for q, (n, S, res) in enumerate(cases)]
+    res = {"metric": "co-scheduled Jacobi region: learned CPU/GPU split vs the better single target",
+           "value": round(geo(pure[test] / sel), 4), "unit": "x (geomean speedup, held-out cases)",
+           "n_gpus": 1, "steps": 0, "warmup": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "cubic FP64 Jacobi grids 128^3..512^3, 1/2/4 sweeps, device- or "
+                                  "pinned-host-resident, host share 0.0..1.0 of the z-planes",
+                      "cases": len(cases), "train_cases": len(train), "test_cases": len(test)},
+           "held_out_geomean_regret_pct": round(100 * (geo(sel / best[test]) - 1), 3),
+           "exhaustive_speedup_over_better_single_geomean": round(geo(pure / best), 4),
+           "cases_where_a_split_wins": int(np.sum((np.argmin(table, axis=1) > 0) &
+                                                  (np.argmin(table, axis=1) < V - 1))),
+           "static_all_gpu_regret_pct": round(100 * (geo(table[:, 0] / best) - 1), 3),
+           "static_all_host_regret_pct": round(100 * (geo(table[:, V - 1] / best) - 1), 3),
+           "train_loss": loss, "table_seconds": round(table_s, 1), "cases_detail": rows}
+    print(json.dumps(res), flush=True)
+
+
 def spmv_kernel_only(variant: int, launches: int = 5):
     """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
     executions."""
@@ -394,7 +471,7 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=None,
                     help="counter-collection mode: run one size-sweep variant at 512^3 only")
     ap.add_argument("--workload", default="size-sweep",
-                    choices=["size-sweep", "batch", "spmv", "relax"],
+                    choices=["size-sweep", "batch", "spmv", "relax", "cosched"],
                     help="size-sweep: the headline line; batch / spmv / relax: the other region lines")
     args = ap.parse_args()
     if args.kernel_only is not None:
@@ -411,6 +488,9 @@ def main():
         return
     if args.workload == "relax":
         relax_workload(args.steps, args.warmup)
+        return
+    if args.workload == "cosched":
+        cosched_workload(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "

@@ -97,6 +97,13 @@ enum ao_family {
     AO_FAM_JACOBI_ZREG_T4 = 6, /* GPU: four sweeps fused per pass; bx = 64, by (1|2|3|4),
                                   bz planes; S mod 4 sweeps run first as one single, two-
                                   or three-sweep pass */
+    AO_FAM_JACOBI_COSCHED = 7, /* host CPU + GPU together (target AO_TARGET_GPU): the first
+                                  round(nz * bx / 10) z-planes sweep on the host (OpenMP,
+                                  whole rows in tiles of 8), the rest on the GPU (register
+                                  z-march, 2 rows per wave, 16 planes), one halo plane
+                                  exchanged each way after every sweep; bx = 0..10 (the
+                                  host's share in tenths), by = bz = 0; timed with a
+                                  steady clock and synchronous */
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
     AO_FAM_SPMV_MERGE_PATH = 12  /* GPU: nnz-balanced row-aligned chunks, blocks of bx */

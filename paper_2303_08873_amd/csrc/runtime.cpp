@@ -178,7 +178,8 @@ int validate_variant(int kind, const ao_variant& v, int id) {
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "unknown target");
         if (v.family != AO_FAM_JACOBI_DIRECT && v.family != AO_FAM_JACOBI_ZMARCH &&
             v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2 &&
-            v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4)
+            v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4 &&
+            v.family != AO_FAM_JACOBI_COSCHED)
             return fail(AO_EINVAL, at + "unknown GPU Jacobi family");
         if (v.family == AO_FAM_JACOBI_ZREG_T2 &&
             (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
@@ -189,6 +190,11 @@ int validate_variant(int kind, const ao_variant& v, int id) {
                              v.by == 8) ||
              v.bz <= 0))
             return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1|2|3|4|6|8, bz > 0");
+        if (v.family == AO_FAM_JACOBI_COSCHED) {
+            if (v.bx < 0 || v.bx > 10 || v.by != 0 || v.bz != 0)
+                return fail(AO_EINVAL, at + "co-scheduling needs bx 0..10 (host tenths), by = bz = 0");
+            return AO_OK;
+        }
         if (v.family == AO_FAM_JACOBI_ZREG_T4 &&
             (v.bx != 64 || v.by < 1 || v.by > 4 || v.bz <= 0))
             return fail(AO_EINVAL, at + "four-sweep z-march needs bx 64, by 1..4, bz > 0");
@@ -391,6 +397,96 @@ int compute_features(ao_region* r, const ao_args* a, hipStream_t s, float* f) {
     return AO_OK;
 }
 
+// CPU+GPU co-scheduling of one Jacobi execution (the co-scheduling use
+// case, Sec. 3.2): planes [0, kc) sweep on the host, planes [kc, nz) on the
+// GPU, kc = round(nz * bx / 10).  Each side sweeps a sub-grid that carries
+// the other side's boundary plane as a halo (its own output for that plane
+// is discarded), the GPU asynchronously while the host team works; after the
+// sweep the new boundary planes cross (one plane each way).  Every plane is
+// computed with the region's arithmetic, so the result is bit-identical to
+// any single-target variant.  Synchronous; timed with the steady clock.
+int run_cosched(ao_region* r, const ao_variant& v, const ao_args* a, hipStream_t s,
+                double* secs) {
+    const int nx = a->nx, ny = a->ny, nz = a->nz, S = a->sweeps;
+    const size_t plane = (size_t)nx * ny, n = plane * nz;
+    const int kc = (int)(((int64_t)nz * v.bx + 5) / 10);
+    const bool host_part = kc > 0, gpu_part = kc < nz;
+    const int gb = host_part ? kc - 1 : 0;           // first plane of the GPU sub-grid
+    const int hz = gpu_part ? kc + 1 : nz;           // planes of the host sub-grid
+    const ao_variant gin{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, 2, 16, v.flags & AO_VF_NT_STORE};
+    const ao_variant hin{AO_TARGET_HOST, AO_FAM_JACOBI_HOST, 0, 8, 1, 0};
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(AO_EHIP, hip_msg("stream sync", e));
+    if (n > 0 && gpu_part) {
+        int rc = ensure_dev(r, n);
+        if (rc) return rc;
+    }
+    if (n > 0 && host_part && a->resident) {
+        int rc = ensure_host(r, (size_t)hz * plane);
+        if (rc) return rc;
+    }
+    if (n > 0 && !a->resident && S >= 2 && r->host_tmp.size() < n) r->host_tmp.assign(n, 0.0);
+    const uint64_t t0 = now_ns();
+    auto copy = [&](void* dst, const void* src, size_t bytes, hipMemcpyKind k) {
+        if (e == hipSuccess && bytes > 0) e = hipMemcpyAsync(dst, src, bytes, k, s);
+    };
+    if (n > 0 && S == 0) {
+        copy(a->out, a->u0, n * 8, a->resident ? hipMemcpyDeviceToDevice : hipMemcpyHostToHost);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    } else if (n > 0) {
+        // sweep-0 sources; the device chain ends in the device result buffer,
+        // the host chain in the host one
+        const double* dsrc = nullptr;
+        const double* hsrc = nullptr;
+        if (a->resident) {
+            dsrc = a->u0;
+            if (host_part) copy(r->h_a, a->u0, (size_t)hz * plane * 8, hipMemcpyDeviceToHost);
+            hsrc = r->h_a;
+        } else {
+            hsrc = a->u0;
+            if (gpu_part)
+                copy(r->d_a + (size_t)gb * plane, a->u0 + (size_t)gb * plane,
+                     (size_t)(nz - gb) * plane * 8, hipMemcpyHostToDevice);
+            dsrc = r->d_a;
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (int k = 0; k < S && e == hipSuccess; ++k) {
+            const bool last = (S - 1 - k) % 2 == 0;
+            double* ddst = a->resident ? (last ? a->out : r->d_a) : (k % 2 == 0 ? r->d_b : r->d_a);
+            double* hdst = a->resident ? (k % 2 == 0 ? r->h_b : r->h_a)
+                                       : (last ? a->out : r->host_tmp.data());
+            if (gpu_part)
+                e = jacobi_gpu_sweep(gin, dsrc + (size_t)gb * plane, ddst + (size_t)gb * plane, nx,
+                                     ny, nz - gb, s);
+            if (e == hipSuccess && host_part)
+                jacobi_host_sweeps(hin, hsrc, hdst, nullptr, nx, ny, hz, 1);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (host_part && gpu_part) {  // the new boundary planes cross
+                copy(ddst + (size_t)(kc - 1) * plane, hdst + (size_t)(kc - 1) * plane, plane * 8,
+                     hipMemcpyHostToDevice);
+                copy(hdst + (size_t)kc * plane, ddst + (size_t)kc * plane, plane * 8,
+                     hipMemcpyDeviceToHost);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+            }
+            dsrc = ddst;
+            hsrc = hdst;
+        }
+        // assemble: the other side's planes into the result
+        if (a->resident && host_part)
+            copy(a->out, hsrc, (size_t)kc * plane * 8, hipMemcpyHostToDevice);
+        if (!a->resident && gpu_part)
+            copy(a->out + (size_t)kc * plane, dsrc + (size_t)kc * plane,
+                 (size_t)(nz - kc) * plane * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AO_EHIP, hip_msg("co-scheduled variant", e));
+    }
+    *secs = (double)(now_ns() - t0) * 1e-9;
+    return AO_OK;
+}
+
 // Enqueue / run variant `vid` once.  When `sync` is set the call waits and
 // returns the time in *secs; otherwise GPU timings are left pending with
 // record index `rec` (host variants always return *secs).
@@ -402,6 +498,7 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
     if (r->kind == AO_JACOBI7_F64) {
         const int nx = a->nx, ny = a->ny, nz = a->nz, S = a->sweeps;
         const size_t n = (size_t)nx * ny * nz;
+        if (v.family == AO_FAM_JACOBI_COSCHED) return run_cosched(r, v, a, s, secs);
         if (v.target == AO_TARGET_GPU) {
             int rc = ensure_dev(r, std::max<size_t>(n, 1));
             if (rc) return rc;

@@ -222,6 +222,37 @@ def test_three_and_four_sweep_families_all_shapes(env, orc, shape, S):
         ao.region_destroy(h)
 
 
+@pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((64, 32, 16), 2), ((7, 5, 1), 2),
+                                     ((33, 65, 10), 5), ((20, 20, 3), 0), ((70, 9, 2), 1)])
+def test_cosched_every_fraction_both_residencies(env, orc, shape, S):
+    # CPU+GPU co-scheduling: the host's share of z-planes in tenths 0..10,
+    # one halo plane exchanged each way per sweep; bit-identical to S sweeps
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=81 + nz + S)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_COSCHED, f, 0, 0, f % 2) for f in range(11)]
+    h = ao.region_declare_variants(f"gpu_cosched_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                   model_type="roundrobin")
+    for resident in (1, 0):
+        if resident:
+            a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+        else:
+            uh = torch.from_numpy(u0_h).pin_memory()
+            oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
+            a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
+        for v in range(len(vs)):
+            (out if resident else oh).fill_(-1.0)
+            ao.region_run(h, a, stream=st, variant=v)
+            torch.cuda.synchronize()
+            _check((out if resident else oh).cpu().numpy(), want)
+        if not resident:
+            assert np.array_equal(uh.numpy(), u0_h)   # the input is untouched
+    ao.region_destroy(h)
+
+
 def test_hbm_copy_probe(env):
     ao, torch, dev, st = env
     for n in (0, 1, 5, 4096, 1000003):

@@ -135,6 +135,12 @@ def test_argument_errors(ao):
     ao.region_destroy(ao.region_declare_variants("t3rows", ao.AO_JACOBI7_F64, ok))
     ok = [ao.Variant(G, ao.FAM_JACOBI_ZREG_T4, 64, r, 8, 1) for r in (1, 2, 3, 4)]
     ao.region_destroy(ao.region_declare_variants("t4rows", ao.AO_JACOBI7_F64, ok))
+    ok = [ao.Variant(G, ao.FAM_JACOBI_COSCHED, f, 0, 0, 0) for f in range(11)]
+    ao.region_destroy(ao.region_declare_variants("cosched_ok", ao.AO_JACOBI7_F64, ok))
+    for bad in ((11, 0, 0), (-1, 0, 0), (5, 1, 0), (5, 0, 2)):
+        with pytest.raises(ao.AdaptError):
+            ao.region_declare_variants(f"cosched_bad_{bad}", ao.AO_JACOBI7_F64,
+                                       [ao.Variant(G, ao.FAM_JACOBI_COSCHED, *bad, 0)])
     ao.region_destroy(h)
 
 
