@@ -106,7 +106,12 @@ enum ao_family {
                                   steady clock and synchronous */
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
-    AO_FAM_SPMV_MERGE_PATH = 12  /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
+    AO_FAM_SPMV_MERGE_PATH = 12, /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
+    AO_FAM_SPMV_BANDED = 13      /* GPU: columns cut into by (8|16|32; 0 = 16) bands so that
+                                    each XCD gathers x from a slice held in its L2: the
+                                    values are copied band-major, products are formed band
+                                    by band, then summed per row by merge-path (blocks of
+                                    bx); a per-matrix plan of about 20 B per nonzero */
 };
 
 /* variant flags */

@@ -18,7 +18,7 @@ FAM_JACOBI_ZREG_T2 = 4
 FAM_JACOBI_ZREG_T3 = 5
 FAM_JACOBI_ZREG_T4 = 6
 FAM_JACOBI_COSCHED = 7
-FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH = 10, 11, 12
+FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH, FAM_SPMV_BANDED = 10, 11, 12, 13
 AO_VF_NT_STORE = 1
 AO_VF_HALO_PREFETCH = 2
 AO_VF_OCCUPANCY = 4

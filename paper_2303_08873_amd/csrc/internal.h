@@ -54,10 +54,26 @@ struct SpmvPlan {
         int32_t* sunit = nullptr;   // [blocks + 1] start unit within that row
     };
     std::vector<MergeSplit> mp;
+    // banded: columns cut into nb bands; every nonzero gets a place in a
+    // band-major copy (band outer, row inner, row order kept inside a row)
+    struct Banding {
+        int nb = 0;
+        int32_t* bstart = nullptr;  // [nb*n + 1] first band-major place of (band b, row i) at b*n+i
+        int32_t* bcol = nullptr;    // [nnz] column of each band-major place
+        int32_t* bpos = nullptr;    // [nnz] band-major place of CSR entry k
+        std::vector<int64_t> off;   // [nb + 1] first place of each band (host copy)
+        int chunks = 0;             // products workgroups per band (the largest band)
+        int32_t kbeg = 0;           // row_ptr[0]: places count from this CSR entry
+    };
+    std::vector<Banding> bands;
+    double* bval = nullptr;  // [nnz] band-major values (refreshed per execution)
+    double* prod = nullptr;  // [nnz] band-major products
     ~SpmvPlan();
 };
 // Build the merge-path partition for workgroups of B threads (synchronises).
 hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s);
+// Build the banding with nb bands (synchronises); needs the plan's col array.
+hipError_t spmv_prepare_banded(SpmvPlan& p, int nb, const int32_t* col, hipStream_t s);
 
 hipError_t spmv_features(SpmvPlan& p, hipStream_t s);
 // What a finished row i with canonical sum s_i stores: y_i = s_i (b ==
@@ -67,8 +83,12 @@ struct SpmvEpi {
     const double* d = nullptr;
     double omega = 0.0;
 };
+// values_ready: the banded family's band-major copy of val already holds
+// this val (set by the caller for the second and later sweeps of one
+// execution); other families ignore it.
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                    const double* x, double* y, hipStream_t s, const SpmvEpi& ep = SpmvEpi());
+                    const double* x, double* y, hipStream_t s, const SpmvEpi& ep = SpmvEpi(),
+                    bool values_ready = false);
 
 // Cost model kernels.
 struct MlpNorm {

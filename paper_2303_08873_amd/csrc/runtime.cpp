@@ -210,8 +210,12 @@ int validate_variant(int kind, const ao_variant& v, int id) {
     if (kind == AO_CSR_SPMV_F64 || kind == AO_CSR_RELAX_F64) {
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "SpMV variants run on the GPU");
         if (v.family != AO_FAM_SPMV_THREAD_ROW && v.family != AO_FAM_SPMV_WAVE_ROW &&
-            v.family != AO_FAM_SPMV_MERGE_PATH)
+            v.family != AO_FAM_SPMV_MERGE_PATH && v.family != AO_FAM_SPMV_BANDED)
             return fail(AO_EINVAL, at + "unknown SpMV family");
+        if (v.family == AO_FAM_SPMV_BANDED &&
+            ((v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) ||
+             (v.by != 0 && v.by != 8 && v.by != 16 && v.by != 32)))
+            return fail(AO_EINVAL, at + "banded SpMV needs bx 64..1024 (power of 2), by 0|8|16|32");
         if (v.bx <= 0) return fail(AO_EINVAL, at + "block size must be positive");
         if (v.family == AO_FAM_SPMV_WAVE_ROW && v.by != 0 &&
             (v.by < 1 || v.by > 64 || (v.by & (v.by - 1))))
@@ -361,14 +365,18 @@ SpmvPlan* get_plan(ao_region* r, const ao_args* a, hipStream_t s, int* rc) {
         return nullptr;
     }
     p->have_features = true;
-    // merge-path partitions for the region's merge-path variants
+    // merge-path partitions for the region's merge-path and banded variants,
+    // and the banded variants' band plans
     for (const ao_variant& v : r->variants) {
-        if (v.family != AO_FAM_SPMV_MERGE_PATH || p->n <= 0) continue;
+        if ((v.family != AO_FAM_SPMV_MERGE_PATH && v.family != AO_FAM_SPMV_BANDED) || p->n <= 0)
+            continue;
         if (v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) continue;
         e = spmv_prepare_merge(*p, v.bx, s);
+        if (e == hipSuccess && v.family == AO_FAM_SPMV_BANDED)
+            e = spmv_prepare_banded(*p, v.by == 0 ? 16 : v.by, a->col, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            *rc = fail(AO_EHIP, hip_msg("merge-path partition", e));
+            *rc = fail(AO_EHIP, hip_msg("merge-path / band plan", e));
             return nullptr;
         }
     }
@@ -654,7 +662,7 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
         const double* src = a->x;
         for (int k = 0; k < S && e == hipSuccess; ++k) {
             double* dst = ((S - 1 - k) % 2 == 0) ? a->y : r->d_a;
-            e = spmv_gpu(v, *p, a->col, a->val, src, dst, s, ep);
+            e = spmv_gpu(v, *p, a->col, a->val, src, dst, s, ep, k > 0);
             src = dst;
         }
     }
@@ -859,6 +867,13 @@ ao_region::~ao_region() {
 SpmvPlan::~SpmvPlan() {
     for (auto& m : mp)
         if (m.srow) hipFree(m.srow);
+    for (auto& b : bands) {
+        if (b.bstart) hipFree(b.bstart);
+        if (b.bcol) hipFree(b.bcol);
+        if (b.bpos) hipFree(b.bpos);
+    }
+    if (bval) hipFree(bval);
+    if (prod) hipFree(prod);
     if (unit_ptr) hipFree(unit_ptr);
     if (unit_sums) hipFree(unit_sums);
 }

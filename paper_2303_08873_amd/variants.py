@@ -5,8 +5,8 @@ from __future__ import annotations
 
 from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE,
                    FAM_JACOBI_DIRECT,
-                   FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T4, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW,
-                   FAM_SPMV_WAVE_ROW, Variant)
+                   FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T4, FAM_SPMV_BANDED,
+                   FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, Variant)
 
 
 def jacobi_variants_blocks():
@@ -35,11 +35,14 @@ def jacobi_variants_sweep():
     return out
 
 
-def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64):
-    """{thread-per-row, wavefront-per-row, merge-path} x block sizes."""
+def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64, banded=()):
+    """{thread-per-row, wavefront-per-row, merge-path} x block sizes, then the
+    banded family for each (merge-path block size, bands) in `banded`."""
     out = []
     for fam in (FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH):
         for b in blocks:
             out.append(Variant(AO_TARGET_GPU, fam, b, wave_lanes if fam == FAM_SPMV_WAVE_ROW else 0,
                                1, 0))
+    for b, nb in banded:
+        out.append(Variant(AO_TARGET_GPU, FAM_SPMV_BANDED, b, nb, 1, 0))
     return out

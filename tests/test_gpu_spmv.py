@@ -29,6 +29,8 @@ def _variants(ao):
         vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_WAVE_ROW, 256, w, 1, 0))
     for b in (128, 512):
         vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, b, 0, 1, 0))
+    for b, nb in ((256, 8), (1024, 16), (64, 32), (512, 0)):
+        vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_BANDED, b, nb, 1, 0))
     return vs
 
 
