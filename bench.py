@@ -441,7 +441,8 @@ def cosched_workload(steps: int, warmup: int):
 
 def spmv_kernel_only(variant: int, launches: int = 5):
     """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
-    executions."""
+    executions.  Ids 0..8 are the benchmark's table; 9 and 10 are the banded
+    family (merge-path block 256 with 16 and with 8 column bands)."""
     import torch
 
     import paper_2303_08873_amd as ao
@@ -453,7 +454,8 @@ def spmv_kernel_only(variant: int, launches: int = 5):
     t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     region = ao.region_declare_variants("bench_spmv_kernel_only", ao.AO_CSR_SPMV_F64,
-                                        ao.spmv_variants(), model_type="roundrobin")
+                                        ao.spmv_variants(banded=((256, 16), (256, 8))),
+                                        model_type="roundrobin")
     a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
     for _ in range(launches):
         ao.region_run(region, a, stream=stream, variant=variant)
