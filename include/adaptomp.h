@@ -117,7 +117,9 @@ enum ao_family {
 /* variant flags */
 #define AO_VF_NT_STORE 1      /* non-temporal (streaming) stores of the output */
 #define AO_VF_HALO_PREFETCH 2 /* register z-marches: issue the next plane's loads a plane
-                                 ahead (the halo for one sweep; every load for two) */
+                                 ahead (the halo for one sweep; every load for two; for
+                                 three and four, as soon as the first fused sweep has
+                                 consumed the current plane) */
 #define AO_VF_OCCUPANCY 4     /* two-sweep z-march: registers capped for 4 waves per SIMD */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
@@ -137,7 +139,7 @@ typedef struct ao_args {
     /* Jacobi */
     const double* u0;
     double* out;
-    int32_t nx, ny, nz, sweeps;
+    int32_t nx, ny, nz, sweeps; /* nx <= 2^28, nx * ny * nz <= 2^40; else AO_EINVAL */
     /* SpMV (device-resident only) */
     const int32_t* row_ptr;
     const int32_t* col;

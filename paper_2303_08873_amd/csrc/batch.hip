@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
                                                           int nitems, int pass) {
     const int g = (int)gridDim.x;
     const int slot = xcd_slot((int)blockIdx.x, g);
-    const int wave = (int)(threadIdx.x >> 6);
+    const int wave = wave_index();
     for (int w = slot; w < nitems; w += g) {
         const Item it = items[w];
         const Inst in = insts[it.inst];
@@ -395,6 +395,7 @@ int batch_create(const ao_args* inst, int count, ao_batch** out) {
             return fail(AO_EINVAL, "batched instances must be device-resident Jacobi regions");
         if (a.nx < 0 || a.ny < 0 || a.nz < 0 || a.sweeps < 0)
             return fail(AO_EINVAL, "negative size or sweep count");
+        if (a.nx > (1 << 28)) return fail(AO_EINVAL, "nx above 2^28");
         const size_t n = (size_t)a.nx * a.ny * a.nz;
         if (n > 0 && (!a.u0 || !a.out)) return fail(AO_EINVAL, "u0/out is NULL");
         if (n > 0) {

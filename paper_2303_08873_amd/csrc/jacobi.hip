@@ -282,7 +282,7 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     const int bj = (int)(t % (unsigned)nby);
     const int kb = (int)(t / (unsigned)nby);
     const int lane = (int)(threadIdx.x & 63);
-    const int wave = (int)(threadIdx.x >> 6);
+    const int wave = wave_index();
     const int i0 = 62 * bi - 1;
     const int i = i0 + lane;
     const int j0 = (bj * kZregWaves + wave) * R;
@@ -293,9 +293,16 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     const bool xin = i >= 0 && i < nx;
     const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
     const bool eok = (lane == 0 || lane == 63) && ie >= 0 && ie < nx;
-    auto ld = [&](int k, int j, int x, bool ok) -> double {
-        return (ok && k >= 0 && k < nz && j >= 0 && j < ny) ? src[(size_t)k * plane + (size_t)j * nx + x]
-                                                          : 0.0;
+    // unmasked loads at clamped (wave-uniform) rows and planes and clamped x,
+    // zeroed afterwards outside the grid (nx * 8 < 2^32 on the host side)
+    const unsigned bo = (unsigned)min(max(i, 0), nx - 1) * 8u;
+    const unsigned boe = (unsigned)min(max(ie, 0), nx - 1) * 8u;
+    auto ld = [&](int k, int j, unsigned off, bool ok) -> double {
+        const bool in = k >= 0 && k < nz && j >= 0 && j < ny;  // wave-uniform
+        const int kc = min(max(k, 0), nz - 1), jc = min(max(j, 0), ny - 1);
+        const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)jc * nx));
+        const double v = *(const double*)(row + off);
+        return (ok && in) ? v : 0.0;
     };
     // registers hold only the rows each plane is read at:
     //   um[q] = u(k-1) on rows j0-1+q   (centre rows of v)
@@ -305,9 +312,9 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     double um[RV], uc[RU], up[RU];
     double vm[R], vc[RV], vn[RV];
 #pragma unroll
-    for (int q = 0; q < RV; ++q) um[q] = ld(k0 - 2, j0 - 1 + q, i, xin);
+    for (int q = 0; q < RV; ++q) um[q] = ld(k0 - 2, j0 - 1 + q, bo, xin);
 #pragma unroll
-    for (int q = 0; q < RU; ++q) uc[q] = ld(k0 - 1, j0 - 2 + q, i, xin);
+    for (int q = 0; q < RU; ++q) uc[q] = ld(k0 - 1, j0 - 2 + q, bo, xin);
 #pragma unroll
     for (int r = 0; r < R; ++r) vm[r] = 0.0;  // v(k0-3) is never read
 #pragma unroll
@@ -315,9 +322,9 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
     double upn[PF ? RU : 1], exn[PF ? RV : 1];
     if constexpr (PF) {
 #pragma unroll
-        for (int q = 0; q < RU; ++q) upn[q] = ld(k0, j0 - 2 + q, i, xin);
+        for (int q = 0; q < RU; ++q) upn[q] = ld(k0, j0 - 2 + q, bo, xin);
 #pragma unroll
-        for (int q = 0; q < RV; ++q) exn[q] = ld(k0 - 1, j0 - 1 + q, ie, eok);
+        for (int q = 0; q < RV; ++q) exn[q] = ld(k0 - 1, j0 - 1 + q, boe, eok);
     }
     for (int k = k0 - 1; k <= k1; ++k) {
         double ex[RV];
@@ -328,15 +335,15 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
             for (int q = 0; q < RV; ++q) ex[q] = exn[q];
             if (k < k1) {  // wave-uniform; plane k+2 / edges of k+1 for the next iteration
 #pragma unroll
-                for (int q = 0; q < RU; ++q) upn[q] = ld(k + 2, j0 - 2 + q, i, xin);
+                for (int q = 0; q < RU; ++q) upn[q] = ld(k + 2, j0 - 2 + q, bo, xin);
 #pragma unroll
-                for (int q = 0; q < RV; ++q) exn[q] = ld(k + 1, j0 - 1 + q, ie, eok);
+                for (int q = 0; q < RV; ++q) exn[q] = ld(k + 1, j0 - 1 + q, boe, eok);
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < RU; ++q) up[q] = ld(k + 1, j0 - 2 + q, i, xin);
+            for (int q = 0; q < RU; ++q) up[q] = ld(k + 1, j0 - 2 + q, bo, xin);
 #pragma unroll
-            for (int q = 0; q < RV; ++q) ex[q] = ld(k, j0 - 1 + q, ie, eok);
+            for (int q = 0; q < RV; ++q) ex[q] = ld(k, j0 - 1 + q, boe, eok);
         }
         // v(k) on rows j0-1 .. j0+R, all lanes
         const bool kin = k >= 0 && k < nz;
@@ -401,8 +408,9 @@ void jac_zreg_t2_occ(const double* __restrict__ src, double* __restrict__ dst, i
 
 // T sweeps per pass (temporal blocking factor T >= 2), the two-sweep scheme
 // generalised: one wave runs tb_column (zmarch.h) on its 64-lane strip,
-// starting at i0 = (66 - 2T)*bi - (T - 1), storing lanes T-1 .. 64-T.
-template <int T, int R, bool NT>
+// starting at i0 = (66 - 2T)*bi - (T - 1), storing lanes T-1 .. 64-T.  PF
+// selects the march's early next-plane loads.
+template <int T, int R, bool NT, bool PF>
 __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
                                              double* __restrict__ dst, int nx, int ny, int nz,
                                              int nbx, int nby, int bz, unsigned nblocks) {
@@ -412,32 +420,39 @@ __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
     const unsigned t = b / (unsigned)nbx;
     const int bj = (int)(t % (unsigned)nby);
     const int kb = (int)(t / (unsigned)nby);
-    const int wave = (int)(threadIdx.x >> 6);
+    const int wave = wave_index();
     const int j0 = (bj * kZregWaves + wave) * R;
     if (j0 >= ny) return;  // wave-uniform
     const int k0 = kb * bz;
-    zm::tb_column<T, R, NT>(src, dst, nx, ny, nz, W * bi - (T - 1), j0, k0, min(nz, k0 + bz), T - 1,
-                        64 - T);
+    zm::tb_column<T, R, NT, PF>(src, dst, nx, ny, nz, W * bi - (T - 1), j0, k0, min(nz, k0 + bz),
+                                T - 1, 64 - T);
 }
 
-template <int T, int R, bool NT>
+template <int T, int R, bool NT, bool PF>
 __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg_tb(const double* __restrict__ src,
                                                                 double* __restrict__ dst, int nx,
                                                                 int ny, int nz, int nbx, int nby,
                                                                 int bz, unsigned nblocks) {
-    zreg_tb_body<T, R, NT>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+    zreg_tb_body<T, R, NT, PF>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
 }
 
 template <int T, int R>
-hipError_t launch_zreg_tb(bool nt, dim3 grid, hipStream_t s, const double* src, double* dst,
-                          int nx, int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
+hipError_t launch_zreg_tb(bool nt, bool pf, dim3 grid, hipStream_t s, const double* src,
+                          double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
+                          unsigned nb) {
     const dim3 block(64 * kZregWaves);
-    if (nt)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
+    if (nt && pf)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, true>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
+    else if (nt)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
+    else if (pf)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, true>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     else
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false>), grid, block, 0, s, src, dst, nx, ny,
+                           nz, nbx, nby, bz, nb);
     return hipGetLastError();
 }
 
@@ -568,7 +583,7 @@ hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, doubl
                                   int ny, int nz, hipStream_t s) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
     const int R = v.by, bz = v.bz;
-    if (v.family != AO_FAM_JACOBI_ZREG_T2 || v.bx != 64 || bz <= 0)
+    if (v.family != AO_FAM_JACOBI_ZREG_T2 || v.bx != 64 || bz <= 0 || nx > (1 << 28))
         return hipErrorInvalidConfiguration;
     const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
     const bool occ = (v.flags & AO_VF_OCCUPANCY) != 0;
@@ -594,8 +609,9 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
     const int R = v.by, bz = v.bz;
     const int T = v.family == AO_FAM_JACOBI_ZREG_T3 ? 3 : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4 : 0;
-    if (T == 0 || v.bx != 64 || bz <= 0) return hipErrorInvalidConfiguration;
+    if (T == 0 || v.bx != 64 || bz <= 0 || nx > (1 << 28)) return hipErrorInvalidConfiguration;
     const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
+    const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
     const int nbx = cdiv(nx, 66 - 2 * T), nby = cdiv(ny, kZregWaves * R);
     const int64_t nb = (int64_t)nbx * nby * cdiv(nz, bz);
     if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -603,7 +619,7 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
     const unsigned u = (unsigned)nb;
 #define AO_TB(TT, RR)                                                                          \
     if (T == TT && R == RR)                                                                    \
-        return launch_zreg_tb<TT, RR>(nt, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+        return launch_zreg_tb<TT, RR>(nt, pf, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
     AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 6) AO_TB(3, 8)
     AO_TB(4, 1) AO_TB(4, 2) AO_TB(4, 3) AO_TB(4, 4)
 #undef AO_TB

@@ -21,4 +21,11 @@ __device__ __forceinline__ double from_right(double v) {
                             __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
 }
 
+// The wave's index within its block, as a wave-uniform value: the compiler
+// then keeps what derives from it (row indices, row base addresses, row
+// bounds tests) in scalar registers instead of one copy per lane.
+__device__ __forceinline__ int wave_index() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 }  // namespace ao

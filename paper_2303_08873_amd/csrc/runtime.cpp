@@ -234,6 +234,7 @@ int validate_args(const ao_region* r, const ao_args* a) {
         if (a->resident != 0 && a->resident != 1) return fail(AO_EINVAL, "resident must be 0 or 1");
         const int64_t n = (int64_t)a->nx * a->ny * a->nz;
         if (n > ((int64_t)1 << 40)) return fail(AO_EINVAL, "grid too large");
+        if (a->nx > (1 << 28)) return fail(AO_EINVAL, "nx above 2^28");
         if (n > 0 && (!a->u0 || !a->out)) return fail(AO_EINVAL, "u0/out is NULL");
         if (n > 0) {
             const char* u = (const char*)a->u0;

@@ -46,10 +46,10 @@ struct TbShape {
     static constexpr int kBelow = offm(T);
 };
 
-// One level: level L at plane p from level L-1, then the next level.  The
-// arrays are the caller's register arrays; every index is a compile-time
-// constant once inlined, so they stay in registers.
-template <int T, int R, int L, bool NT>
+// One level: level L at plane p from level L-1, then the next level up to
+// STOP.  The arrays are the caller's register arrays; every index is a
+// compile-time constant once inlined, so they stay in registers.
+template <int T, int R, int L, bool NT, int STOP = T>
 __device__ __forceinline__ void tb_level(const double* below, const double* centre,
                                          double* fresh, const double* ex, double* dst,
                                          int k, int j0, int nx, int ny, int nz, int k0, int k1,
@@ -77,29 +77,32 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
             if (lane_out && j < ny) put<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kSixth);
         }
     }
-    if constexpr (L < T)
-        tb_level<T, R, L + 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                                  lane, i, xin, lane_out);
+    if constexpr (L < STOP)
+        tb_level<T, R, L + 1, NT, STOP>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
+                                        plane, lane, i, xin, lane_out);
 }
 
 // Shift every level by one plane: below <- centre (centre rows of the next
 // level), centre <- fresh.
-template <int T, int R, int L>
+template <int T, int R, int L, int STOP = T - 1>
 __device__ __forceinline__ void tb_rotate(double* below, double* centre, const double* fresh) {
     using S = TbShape<T, R>;
 #pragma unroll
     for (int q = 0; q < S::nl(L + 1); ++q) below[S::offm(L) + q] = centre[S::off(L) + q + 1];
 #pragma unroll
     for (int q = 0; q < S::nl(L); ++q) centre[S::off(L) + q] = fresh[S::off(L) + q];
-    if constexpr (L + 1 < T) tb_rotate<T, R, L + 1>(below, centre, fresh);
+    if constexpr (L < STOP) tb_rotate<T, R, L + 1, STOP>(below, centre, fresh);
 }
 
 // T sweeps of src on the wave's column: lanes hold x = i0 + lane, output
 // rows j0 .. j0+R-1 (j0 < ny), output planes [k0, k1); level T is stored on
 // lanes lane_lo .. lane_hi that lie inside the grid (the caller keeps that
 // window within T-1 .. 64-T).  Every load is bounds-checked; the whole wave
-// must call this (cross-lane moves).
-template <int T, int R, bool NT>
+// must call this (cross-lane moves).  EARLY: the next plane's level-0 rows
+// and strip edges are loaded as soon as level 1 has consumed this plane's
+// (into the same registers), so they are in flight while levels 2..T
+// compute instead of at the top of the next iteration.
+template <int T, int R, bool NT, bool EARLY = false>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
                                           int lane_lo, int lane_hi) {
@@ -111,26 +114,61 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
     const int ie = (lane == 0) ? i0 - 1 : i0 + 64;
     const bool eok = (lane == 0 || lane == 63) && ie >= 0 && ie < nx;
     const bool lane_out = lane >= lane_lo && lane <= lane_hi && xin;
-    auto ld = [&](int k, int j, int x, bool ok) -> double {
-        return (ok && k >= 0 && k < nz && j >= 0 && j < ny) ? src[(size_t)k * plane + (size_t)j * nx + x]
-                                                          : 0.0;
+    // Row loads: the row's base address is wave-uniform (j and k are), each
+    // lane reads at its x clamped into the row, and rows and planes outside
+    // the grid are clamped too; the value is zeroed afterwards where the
+    // point lies outside.  No load is masked or branched around (so loads
+    // stay batched ahead of their first use) and one 32-bit byte offset
+    // serves every row (the caller keeps nx * 8 below 2^32).
+    const unsigned bo = (unsigned)min(max(i, 0), nx - 1) * 8u;
+    const unsigned boe = (unsigned)min(max(ie, 0), nx - 1) * 8u;
+    auto ld = [&](int k, int j, unsigned off, bool ok) -> double {
+        const bool in = k >= 0 && k < nz && j >= 0 && j < ny;  // wave-uniform
+        const int kc = min(max(k, 0), nz - 1), jc = min(max(j, 0), ny - 1);
+        const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)jc * nx));
+        const double v = *(const double*)(row + off);
+        return (ok && in) ? v : 0.0;
     };
     double below[S::kBelow], centre[S::kAll], fresh[S::kAll];
     const int ka = k0 - T + 1;  // first iteration: level 1 at plane ka
 #pragma unroll
-    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, i, xin);
+    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, bo, xin);
 #pragma unroll
-    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, i, xin);
+    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, bo, xin);
 #pragma unroll
     for (int q = S::nl(1); q < S::kBelow; ++q) below[q] = 0.0;
 #pragma unroll
     for (int q = S::nl(0); q < S::kAll; ++q) centre[q] = 0.0;
+    if constexpr (EARLY && T >= 2) {
+        const int kend = k1 + T - 2;
+        double ex[S::nl(1)];
+#pragma unroll
+        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(ka + 1, j0 - T + q, bo, xin);
+#pragma unroll
+        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(ka, j0 - (T - 1) + q, boe, eok);
+        for (int k = ka; k <= kend; ++k) {
+            tb_level<T, R, 1, NT, 1>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
+                                     lane, i, xin, lane_out);
+            // level 0 moves on one plane; level 1's new plane stays in fresh
+            tb_rotate<T, R, 0, 0>(below, centre, fresh);
+            if (k < kend) {  // wave-uniform: the next iteration's plane and edges
+#pragma unroll
+                for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 2, j0 - T + q, bo, xin);
+#pragma unroll
+                for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k + 1, j0 - (T - 1) + q, boe, eok);
+            }
+            tb_level<T, R, 2, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
+                                  lane, i, xin, lane_out);
+            tb_rotate<T, R, 1>(below, centre, fresh);
+        }
+        return;
+    }
     for (int k = ka; k <= k1 + T - 2; ++k) {
         double ex[S::nl(1)];
 #pragma unroll
-        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, i, xin);
+        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, bo, xin);
 #pragma unroll
-        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, ie, eok);
+        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, boe, eok);
         tb_level<T, R, 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
                               lane, i, xin, lane_out);
         tb_rotate<T, R, 0>(below, centre, fresh);

@@ -189,6 +189,12 @@ T3 = [(1, 1, 0), (1, 5, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2,
       (6, 9, 0), (6, 1, 1), (8, 4, 0), (8, 32, 1)]
 T4 = [(1, 1, 0), (1, 6, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2, 0), (4, 16, 1),
       (4, 5, 1), (2, 1, 0)]
+# the same families with the early next-plane loads (flag 2, with and without
+# streaming stores)
+T3_PF = [(1, 1, 2), (1, 5, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4, 2, 2),
+         (4, 16, 3), (6, 9, 2), (6, 1, 3), (8, 4, 2), (8, 32, 3)]
+T4_PF = [(1, 1, 2), (1, 6, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4, 2, 2),
+         (4, 16, 3), (4, 5, 3), (2, 1, 2)]
 
 
 @pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
@@ -203,10 +209,12 @@ def test_three_and_four_sweep_families_all_shapes(env, orc, shape, S):
     want = orc.jacobi7(u0_h, nx, ny, nz, S)
     u0 = torch.from_numpy(u0_h).to(dev)
     out = torch.empty_like(u0)
-    for fam, lst in ((ao.FAM_JACOBI_ZREG_T3, T3), (ao.FAM_JACOBI_ZREG_T4, T4)):
+    for tag, fam, lst in (("", ao.FAM_JACOBI_ZREG_T3, T3), ("", ao.FAM_JACOBI_ZREG_T4, T4),
+                          ("pf", ao.FAM_JACOBI_ZREG_T3, T3_PF),
+                          ("pf", ao.FAM_JACOBI_ZREG_T4, T4_PF)):
         vs = [ao.Variant(ao.AO_TARGET_GPU, fam, 64, r, bz, fl) for r, bz, fl in lst]
-        h = ao.region_declare_variants(f"gpu_tb{fam}_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
-                                       model_type="roundrobin")
+        h = ao.region_declare_variants(f"gpu_tb{tag}{fam}_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64,
+                                       vs, model_type="roundrobin")
         for resident in (1, 0):
             if resident:
                 a = ao.jacobi_args(u0, out, nx, ny, nz, S)

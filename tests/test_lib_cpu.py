@@ -107,6 +107,8 @@ def test_argument_errors(ao):
         ao.region_run(h, ao.jacobi_args(u0, out, 2, 2, 2, 1, resident=0), variant=5)
     with pytest.raises(ao.AdaptError):
         ao.region_run(h, ao.jacobi_args(u0, out, -1, 2, 2, 1, resident=0), variant=0)
+    with pytest.raises(ao.AdaptError):  # rows longer than 2^28 (checked before any access)
+        ao.region_run(h, ao.jacobi_args(u0, out, (1 << 28) + 1, 1, 1, 1, resident=0), variant=0)
     bad = ao.Variant(ao.AO_TARGET_HOST, ao.FAM_JACOBI_DIRECT, 64, 1, 1, 0)
     with pytest.raises(ao.AdaptError):
         ao.region_declare_variants("badvar", ao.AO_JACOBI7_F64, [bad])
