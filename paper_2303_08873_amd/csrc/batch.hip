@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
                                                           int nitems, int pass) {
     const int g = (int)gridDim.x;
     const int slot = xcd_slot((int)blockIdx.x, g);
-    const int wave = wave_index();
+    const int wave = (int)(threadIdx.x >> 6);
     for (int w = slot; w < nitems; w += g) {
         const Item it = items[w];
         const Inst in = insts[it.inst];
@@ -219,19 +219,19 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
         const int i0 = it.x0 - 1;
         if (R == 1) {
             if (single)
-                zm::tb_column<1, 1, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<1, 1, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
             else
-                zm::tb_column<2, 1, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<2, 1, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
         } else if (R == 2) {
             if (single)
-                zm::tb_column<1, 2, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<1, 2, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
             else
-                zm::tb_column<2, 2, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<2, 2, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
         } else {
             if (single)
-                zm::tb_column<1, 4, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<1, 4, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
             else
-                zm::tb_column<2, 4, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
+                zm::tb_column<2, 4, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
         }
     }
 }

@@ -101,8 +101,12 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // must call this (cross-lane moves).  EARLY: the next plane's level-0 rows
 // and strip edges are loaded as soon as level 1 has consumed this plane's
 // (into the same registers), so they are in flight while levels 2..T
-// compute instead of at the top of the next iteration.
-template <int T, int R, bool NT, bool EARLY = false>
+// compute instead of at the top of the next iteration.  SROW: the row
+// indices are wave-uniform (the caller's j0 comes from wave_index()), so
+// loads go to clamped rows through scalar row bases; otherwise rows are
+// per-lane values and out-of-grid loads are masked (fewer scalar registers,
+// for kernels that inline several marches).
+template <int T, int R, bool NT, bool EARLY = false, bool SROW = true>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
                                           int lane_lo, int lane_hi) {
@@ -122,19 +126,24 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
     // serves every row (the caller keeps nx * 8 below 2^32).
     const unsigned bo = (unsigned)min(max(i, 0), nx - 1) * 8u;
     const unsigned boe = (unsigned)min(max(ie, 0), nx - 1) * 8u;
-    auto ld = [&](int k, int j, unsigned off, bool ok) -> double {
-        const bool in = k >= 0 && k < nz && j >= 0 && j < ny;  // wave-uniform
-        const int kc = min(max(k, 0), nz - 1), jc = min(max(j, 0), ny - 1);
-        const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)jc * nx));
-        const double v = *(const double*)(row + off);
-        return (ok && in) ? v : 0.0;
+    auto ld = [&](int k, int j, bool edge) -> double {
+        const bool ok = edge ? eok : xin;
+        const bool in = k >= 0 && k < nz && j >= 0 && j < ny;
+        if constexpr (SROW) {
+            const int kc = min(max(k, 0), nz - 1), jc = min(max(j, 0), ny - 1);
+            const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)jc * nx));
+            const double v = *(const double*)(row + (edge ? boe : bo));
+            return (ok && in) ? v : 0.0;
+        } else {
+            return (ok && in) ? src[(size_t)k * plane + (size_t)j * nx + (edge ? ie : i)] : 0.0;
+        }
     };
     double below[S::kBelow], centre[S::kAll], fresh[S::kAll];
     const int ka = k0 - T + 1;  // first iteration: level 1 at plane ka
 #pragma unroll
-    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, bo, xin);
+    for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, false);
 #pragma unroll
-    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, bo, xin);
+    for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, false);
 #pragma unroll
     for (int q = S::nl(1); q < S::kBelow; ++q) below[q] = 0.0;
 #pragma unroll
@@ -143,9 +152,9 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         const int kend = k1 + T - 2;
         double ex[S::nl(1)];
 #pragma unroll
-        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(ka + 1, j0 - T + q, bo, xin);
+        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(ka + 1, j0 - T + q, false);
 #pragma unroll
-        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(ka, j0 - (T - 1) + q, boe, eok);
+        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(ka, j0 - (T - 1) + q, true);
         for (int k = ka; k <= kend; ++k) {
             tb_level<T, R, 1, NT, 1>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
                                      lane, i, xin, lane_out);
@@ -153,9 +162,9 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
             tb_rotate<T, R, 0, 0>(below, centre, fresh);
             if (k < kend) {  // wave-uniform: the next iteration's plane and edges
 #pragma unroll
-                for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 2, j0 - T + q, bo, xin);
+                for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 2, j0 - T + q, false);
 #pragma unroll
-                for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k + 1, j0 - (T - 1) + q, boe, eok);
+                for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k + 1, j0 - (T - 1) + q, true);
             }
             tb_level<T, R, 2, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
                                   lane, i, xin, lane_out);
@@ -166,9 +175,9 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
     for (int k = ka; k <= k1 + T - 2; ++k) {
         double ex[S::nl(1)];
 #pragma unroll
-        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, bo, xin);
+        for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, false);
 #pragma unroll
-        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, boe, eok);
+        for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, true);
         tb_level<T, R, 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
                               lane, i, xin, lane_out);
         tb_rotate<T, R, 0>(below, centre, fresh);
