@@ -424,8 +424,16 @@ __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
     const int j0 = (bj * kZregWaves + wave) * R;
     if (j0 >= ny) return;  // wave-uniform
     const int k0 = kb * bz;
-    zm::tb_column<T, R, NT, PF>(src, dst, nx, ny, nz, W * bi - (T - 1), j0, k0, min(nz, k0 + bz),
-                                T - 1, 64 - T);
+    const int i0 = W * bi - (T - 1);
+    // every column (with the strip-edge loads) and row (with the T-row halo)
+    // the wave touches inside the grid: the march without per-lane selects
+    const bool inner = i0 >= 1 && i0 + 64 < nx && j0 >= T && j0 + R + T <= ny;  // wave-uniform
+    if (inner)
+        zm::tb_column<T, R, NT, PF, true, true>(src, dst, nx, ny, nz, i0, j0, k0, min(nz, k0 + bz),
+                                                T - 1, 64 - T);
+    else
+        zm::tb_column<T, R, NT, PF>(src, dst, nx, ny, nz, i0, j0, k0, min(nz, k0 + bz), T - 1,
+                                    64 - T);
 }
 
 template <int T, int R, bool NT, bool PF>

@@ -48,8 +48,10 @@ struct TbShape {
 
 // One level: level L at plane p from level L-1, then the next level up to
 // STOP.  The arrays are the caller's register arrays; every index is a
-// compile-time constant once inlined, so they stay in registers.
-template <int T, int R, int L, bool NT, int STOP = T>
+// compile-time constant once inlined, so they stay in registers.  INNER:
+// every row and column the wave touches lies inside the grid, so only whole
+// planes can lie outside (a wave-uniform test instead of per-lane selects).
+template <int T, int R, int L, bool NT, int STOP = T, bool INNER = false>
 __device__ __forceinline__ void tb_level(const double* below, const double* centre,
                                          double* fresh, const double* ex, double* dst,
                                          int k, int j0, int nx, int ny, int nz, int k0, int k1,
@@ -72,14 +74,24 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
         v = v + below[S::offm(L - 1) + q];
         v = v + fresh[S::off(L - 1) + q + 1];
         if constexpr (L < T) {
-            fresh[S::off(L) + q] = (pin && xin && j >= 0 && j < ny) ? v * kSixth : 0.0;
+            if constexpr (INNER)
+                fresh[S::off(L) + q] = v * kSixth;
+            else
+                fresh[S::off(L) + q] = (pin && xin && j >= 0 && j < ny) ? v * kSixth : 0.0;
         } else {
-            if (lane_out && j < ny) put<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kSixth);
+            if (lane_out && (INNER || j < ny))
+                put<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kSixth);
+        }
+    }
+    if constexpr (INNER && L < T) {
+        if (!pin) {  // wave-uniform: the plane lies outside the grid
+#pragma unroll
+            for (int q = 0; q < S::nl(L); ++q) fresh[S::off(L) + q] = 0.0;
         }
     }
     if constexpr (L < STOP)
-        tb_level<T, R, L + 1, NT, STOP>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
-                                        plane, lane, i, xin, lane_out);
+        tb_level<T, R, L + 1, NT, STOP, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0,
+                                               k1, plane, lane, i, xin, lane_out);
 }
 
 // Shift every level by one plane: below <- centre (centre rows of the next
@@ -106,7 +118,7 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // loads go to clamped rows through scalar row bases; otherwise rows are
 // per-lane values and out-of-grid loads are masked (fewer scalar registers,
 // for kernels that inline several marches).
-template <int T, int R, bool NT, bool EARLY = false, bool SROW = true>
+template <int T, int R, bool NT, bool EARLY = false, bool SROW = true, bool INNER = false>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
                                           int lane_lo, int lane_hi) {
@@ -129,7 +141,11 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
     auto ld = [&](int k, int j, bool edge) -> double {
         const bool ok = edge ? eok : xin;
         const bool in = k >= 0 && k < nz && j >= 0 && j < ny;
-        if constexpr (SROW) {
+        if constexpr (INNER) {  // rows and columns inside: no clamp, no select
+            const int kc = min(max(k, 0), nz - 1);
+            const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)j * nx));
+            return *(const double*)(row + (edge ? boe : bo));
+        } else if constexpr (SROW) {
             const int kc = min(max(k, 0), nz - 1), jc = min(max(j, 0), ny - 1);
             const char* row = (const char*)(src + ((size_t)kc * plane + (size_t)jc * nx));
             const double v = *(const double*)(row + (edge ? boe : bo));
@@ -138,12 +154,23 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
             return (ok && in) ? src[(size_t)k * plane + (size_t)j * nx + (edge ? ie : i)] : 0.0;
         }
     };
+    // INNER loads read a clamped plane; a plane outside the grid is zeroed
+    // after its loads are issued (wave-uniform)
+    auto zero_out = [&](int k, double* a, int n) {
+        if constexpr (INNER) {
+            if (k < 0 || k >= nz) {
+                for (int q = 0; q < n; ++q) a[q] = 0.0;
+            }
+        }
+    };
     double below[S::kBelow], centre[S::kAll], fresh[S::kAll];
     const int ka = k0 - T + 1;  // first iteration: level 1 at plane ka
 #pragma unroll
     for (int q = 0; q < S::nl(1); ++q) below[q] = ld(ka - 1, j0 - (T - 1) + q, false);
 #pragma unroll
     for (int q = 0; q < S::nl(0); ++q) centre[q] = ld(ka, j0 - T + q, false);
+    zero_out(ka - 1, below, S::nl(1));
+    zero_out(ka, centre, S::nl(0));
 #pragma unroll
     for (int q = S::nl(1); q < S::kBelow; ++q) below[q] = 0.0;
 #pragma unroll
@@ -155,9 +182,11 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(ka + 1, j0 - T + q, false);
 #pragma unroll
         for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(ka, j0 - (T - 1) + q, true);
+        zero_out(ka + 1, fresh, S::nl(0));
+        zero_out(ka, ex, S::nl(1));
         for (int k = ka; k <= kend; ++k) {
-            tb_level<T, R, 1, NT, 1>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                                     lane, i, xin, lane_out);
+            tb_level<T, R, 1, NT, 1, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
+                                            plane, lane, i, xin, lane_out);
             // level 0 moves on one plane; level 1's new plane stays in fresh
             tb_rotate<T, R, 0, 0>(below, centre, fresh);
             if (k < kend) {  // wave-uniform: the next iteration's plane and edges
@@ -165,9 +194,11 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
                 for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 2, j0 - T + q, false);
 #pragma unroll
                 for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k + 1, j0 - (T - 1) + q, true);
+                zero_out(k + 2, fresh, S::nl(0));
+                zero_out(k + 1, ex, S::nl(1));
             }
-            tb_level<T, R, 2, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                                  lane, i, xin, lane_out);
+            tb_level<T, R, 2, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
+                                            plane, lane, i, xin, lane_out);
             tb_rotate<T, R, 1>(below, centre, fresh);
         }
         return;
@@ -178,8 +209,10 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 1, j0 - T + q, false);
 #pragma unroll
         for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(k, j0 - (T - 1) + q, true);
-        tb_level<T, R, 1, NT>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1, plane,
-                              lane, i, xin, lane_out);
+        zero_out(k + 1, fresh, S::nl(0));
+        zero_out(k, ex, S::nl(1));
+        tb_level<T, R, 1, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
+                                        plane, lane, i, xin, lane_out);
         tb_rotate<T, R, 0>(below, centre, fresh);
     }
 }

@@ -199,10 +199,13 @@ T4_PF = [(1, 1, 2), (1, 6, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4,
 
 @pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
                                      ((257, 3, 4), 1), ((64, 32, 16), 6), ((6, 6, 6), 5),
-                                     ((61, 5, 7), 7), ((125, 18, 33), 9), ((60, 60, 3), 8)])
+                                     ((61, 5, 7), 7), ((125, 18, 33), 9), ((60, 60, 3), 8),
+                                     ((190, 41, 19), 8)])
 def test_three_and_four_sweep_families_all_shapes(env, orc, shape, S):
     # three / four sweeps fused per pass (the S mod T remaining sweeps first as
-    # one shorter pass), bit-identical to S separate sweeps
+    # one shorter pass), bit-identical to S separate sweeps; the wider shapes
+    # have waves whose columns and rows lie inside the grid (the march
+    # without per-lane selects) beside waves on the boundary
     ao, torch, dev, st = env
     nx, ny, nz = shape
     u0_h = synth.grid_u01(nx, ny, nz, seed=71 + nx + S)
