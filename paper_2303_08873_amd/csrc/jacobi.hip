@@ -351,9 +351,7 @@ __device__ __forceinline__ void zreg_t2_body(const double* __restrict__ src,
         for (int q = 0; q < RV; ++q) {
             const int j = j0 - 1 + q;
             const double c = uc[q + 1];
-            const double left = from_left(c), right = from_right(c);
-            const double xm = (lane == 0) ? ex[q] : left;
-            const double xp = (lane == 63) ? ex[q] : right;
+            const double xm = from_left_or(c, ex[q]), xp = from_right_or(c, ex[q]);
             double v = xm + xp;
             v = v + uc[q];
             v = v + uc[q + 2];

@@ -21,6 +21,23 @@ __device__ __forceinline__ double from_right(double v) {
                             __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
 }
 
+// The same moves with a fill: lane 0 (from_left_or) or lane 63
+// (from_right_or) receives its own `fill` instead of 0 -- the DPP move
+// leaves a lane with no source unwritten (bound_ctrl off), so the strip
+// edge costs a copy of `fill` instead of a select per half.
+__device__ __forceinline__ double from_left_or(double v, double fill) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(
+        __builtin_amdgcn_update_dpp(__double2hiint(fill), hi, 0x138, 0xf, 0xf, false),
+        __builtin_amdgcn_update_dpp(__double2loint(fill), lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_right_or(double v, double fill) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(
+        __builtin_amdgcn_update_dpp(__double2hiint(fill), hi, 0x130, 0xf, 0xf, false),
+        __builtin_amdgcn_update_dpp(__double2loint(fill), lo, 0x130, 0xf, 0xf, false));
+}
+
 // The wave's index within its block, as a wave-uniform value: the compiler
 // then keeps what derives from it (row indices, row base addresses, row
 // bounds tests) in scalar registers instead of one copy per lane.

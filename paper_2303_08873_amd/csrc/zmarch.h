@@ -65,9 +65,9 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
     for (int q = 0; q < S::nl(L); ++q) {
         const int j = jl + q;
         const double c = centre[S::off(L - 1) + q + 1];
-        const double left = from_left(c), right = from_right(c);
-        const double xm = (L == 1 && lane == 0) ? ex[q] : left;
-        const double xp = (L == 1 && lane == 63) ? ex[q] : right;
+        // level 1 takes lane 0's and lane 63's outer neighbours from ex
+        const double xm = L == 1 ? from_left_or(c, ex[q]) : from_left(c);
+        const double xp = L == 1 ? from_right_or(c, ex[q]) : from_right(c);
         double v = xm + xp;
         v = v + centre[S::off(L - 1) + q];
         v = v + centre[S::off(L - 1) + q + 2];
