@@ -51,11 +51,14 @@ struct TbShape {
 // compile-time constant once inlined, so they stay in registers.  INNER:
 // every row and column the wave touches lies inside the grid, so only whole
 // planes can lie outside (a wave-uniform test instead of per-lane selects).
+// hold (non-null): level T is written there instead of stored (the caller
+// stores it later).
 template <int T, int R, int L, bool NT, int STOP = T, bool INNER = false>
 __device__ __forceinline__ void tb_level(const double* below, const double* centre,
                                          double* fresh, const double* ex, double* dst,
                                          int k, int j0, int nx, int ny, int nz, int k0, int k1,
-                                         size_t plane, int lane, int i, bool xin, bool lane_out) {
+                                         size_t plane, int lane, int i, bool xin, bool lane_out,
+                                         double* hold = nullptr) {
     using S = TbShape<T, R>;
     const int p = k - L + 1;
     if (L == T && !(p >= k0 && p < k1)) return;  // wave-uniform
@@ -78,6 +81,8 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
                 fresh[S::off(L) + q] = v * kSixth;
             else
                 fresh[S::off(L) + q] = (pin && xin && j >= 0 && j < ny) ? v * kSixth : 0.0;
+        } else if (hold) {
+            hold[q] = v * kSixth;
         } else {
             if (lane_out && (INNER || j < ny))
                 put<NT>(dst + (size_t)p * plane + (size_t)j * nx + i, v * kSixth);
@@ -91,7 +96,7 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
     }
     if constexpr (L < STOP)
         tb_level<T, R, L + 1, NT, STOP, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0,
-                                               k1, plane, lane, i, xin, lane_out);
+                                               k1, plane, lane, i, xin, lane_out, hold);
 }
 
 // Shift every level by one plane: below <- centre (centre rows of the next
@@ -113,7 +118,10 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // must call this (cross-lane moves).  EARLY: the next plane's level-0 rows
 // and strip edges are loaded as soon as level 1 has consumed this plane's
 // (into the same registers), so they are in flight while levels 2..T
-// compute instead of at the top of the next iteration.  SROW: the row
+// compute instead of at the top of the next iteration; level T is then
+// stored one iteration late, just before those loads are issued, so the
+// loads are always the youngest memory operations and waiting for them
+// never waits for stores issued after them.  SROW: the row
 // indices are wave-uniform (the caller's j0 comes from wave_index()), so
 // loads go to clamped rows through scalar row bases; otherwise rows are
 // per-lane values and out-of-grid loads are masked (fewer scalar registers,
@@ -184,11 +192,24 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         for (int q = 0; q < S::nl(1); ++q) ex[q] = ld(ka, j0 - (T - 1) + q, true);
         zero_out(ka + 1, fresh, S::nl(0));
         zero_out(ka, ex, S::nl(1));
+        double hold[R];
+        int hold_p = -1;  // plane of hold (wave-uniform); stored when in [k0, k1)
+        auto store_hold = [&]() {
+            if (hold_p >= k0 && hold_p < k1) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int j = j0 + q;
+                    if (lane_out && (INNER || j < ny))
+                        put<NT>(dst + (size_t)hold_p * plane + (size_t)j * nx + i, hold[q]);
+                }
+            }
+        };
         for (int k = ka; k <= kend; ++k) {
             tb_level<T, R, 1, NT, 1, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
                                             plane, lane, i, xin, lane_out);
             // level 0 moves on one plane; level 1's new plane stays in fresh
             tb_rotate<T, R, 0, 0>(below, centre, fresh);
+            store_hold();
             if (k < kend) {  // wave-uniform: the next iteration's plane and edges
 #pragma unroll
                 for (int q = 0; q < S::nl(0); ++q) fresh[q] = ld(k + 2, j0 - T + q, false);
@@ -198,9 +219,11 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
                 zero_out(k + 1, ex, S::nl(1));
             }
             tb_level<T, R, 2, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0, k1,
-                                            plane, lane, i, xin, lane_out);
+                                            plane, lane, i, xin, lane_out, hold);
+            hold_p = k - T + 1;
             tb_rotate<T, R, 1>(below, centre, fresh);
         }
+        store_hold();
         return;
     }
     for (int k = ka; k <= k1 + T - 2; ++k) {
