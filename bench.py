@@ -4,12 +4,16 @@ Workload: the size sweep -- cubic FP64 grids 16^3 .. 512^3, 20 sweeps each,
 u0 ~ U[0,1) (seed 2000 + log2 n), device-resident, one region with 10
 variants (5 GPU block / tile shapes, 5 host-CPU tilings).  Set-up
 (untimed): every variant is profiled at every size (the exhaustive
-selector), the records train the cost model on the GPU.  One timed step =
-one region_run per size with the learned selector choosing the variant.
+selector), the records train the cost model on the GPU, and the table is
+taken once more with the grid in pinned host memory (the host / GPU
+crossover per residency).  One timed step = one region_run per size with
+the learned selector choosing the variant.
 
 Printed: one JSON line with the aggregate region GB/s (algorithmic bytes
 16*N*S / time), % of HBM peak, the exhaustive-best GB/s and the selector's
-regret, the roofline of the dominant kernel and the oracle CPU baseline.
+regret, per-size GB/s of every variant for both residencies, the roofline
+of the dominant kernel and the oracle CPU baseline.  Other workloads
+(--workload): batch, spmv, relax, cosched, blocks.
 """
 from __future__ import annotations
 
@@ -50,6 +54,68 @@ def cpu_baseline(repeats=2):
     return {"value": round(total / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"serial C oracle, the full size sweep (16^3..512^3 x 20 sweeps) x {repeats} "
                       f"({dt:.1f} s)"}
+
+
+def host_description():
+    """Host threads and CPU model for the host-variant rows."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"logical_cpus": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": model}
+
+
+def blocks_workload(steps: int, warmup: int):
+    """The threads-per-block use case: a 64^3 FP64 grid (seed 1), 10 sweeps,
+    the one-point-per-thread kernel with 64 / 256 / 1024 threads per block.
+    Every variant is timed (warmup 3, median of 10; the exhaustive pick is
+    the fastest), then `steps` region runs of the pick are timed with HIP
+    events.  The 4 MiB working set is cache-resident: the figures are
+    launch- and cache-bound, not an HBM claim.  Prints one JSON line."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n, S = 64, 10
+    u0 = synth.grid_u01_torch(n, n, n, seed=1, device=dev)
+    out = torch.empty_like(u0)
+    variants = ao.jacobi_variants_blocks()
+    region = ao.region_declare_variants("bench_blocks", ao.AO_JACOBI7_F64, variants,
+                                        model_type="exhaustive")
+    a = ao.jacobi_args(u0, out, n, n, n, S)
+    med = ao.region_profile(region, a, warmup=3, reps=10, stream=stream)
+    alg = 16.0 * n ** 3 * S
+    pick = int(np.argmin(med))
+    for _ in range(warmup):
+        ao.region_run(region, a, stream=stream, variant=pick)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ao.region_run(region, a, stream=stream, variant=pick)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({
+        "metric": "region GB/s (threads-per-block variants, 64^3 x 10 sweeps, cache-resident)",
+        "value": round(alg / (ms * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "7-point FP64 Jacobi, 64^3 (seed 1), 10 sweeps, device-resident; "
+                               "one point per thread, 64 / 256 / 1024 threads per block"},
+        "threads_per_block": [v.bx * v.by for v in variants],
+        "gbs_per_variant": [round(alg / t / 1e9, 2) for t in med],
+        "ms_per_variant": [round(t * 1e3, 4) for t in med],
+        "exhaustive_pick": pick,
+        "note": "4 MiB per array: cache-resident and launch-bound"}), flush=True)
 
 
 def pmc_traffic(variant_key):
@@ -473,8 +539,8 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=None,
                     help="counter-collection mode: run one size-sweep variant at 512^3 only")
     ap.add_argument("--workload", default="size-sweep",
-                    choices=["size-sweep", "batch", "spmv", "relax", "cosched"],
-                    help="size-sweep: the headline line; batch / spmv / relax: the other region lines")
+                    choices=["size-sweep", "batch", "spmv", "relax", "cosched", "blocks"],
+                    help="size-sweep: the headline line; the others: the other region lines")
     args = ap.parse_args()
     if args.kernel_only is not None:
         if args.workload == "spmv":
@@ -493,6 +559,9 @@ def main():
         return
     if args.workload == "cosched":
         cosched_workload(args.steps, args.warmup)
+        return
+    if args.workload == "blocks":
+        blocks_workload(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
@@ -532,6 +601,24 @@ def main():
         _log(f"profiled n={n}: " + " ".join(f"{t * 1e3:.3f}" for t in med) + " ms")
     loss = ao.selector_train(region, epochs=400, batch=64, lr=3e-3, seed=7)
     _log(f"selector trained, final loss {loss:.4g}")
+
+    # the same table with the grid in pinned host memory (GPU variants then
+    # include the transfers both ways), not recorded: the host / GPU
+    # crossover per residency
+    table_host = {}
+    for n in SIZES:
+        u0, _ = grids[n]
+        hu = u0.cpu().pin_memory()
+        ho = torch.empty_like(hu).pin_memory()
+        a = ao.jacobi_args(hu, ho, n, n, n, SWEEPS, resident=0)
+        med = []
+        for v in range(V):
+            gpu = v < 5
+            med.append(ao.region_profile(region, a, variant=v, warmup=1 if gpu else 0,
+                                         reps=3 if gpu else 1, stream=stream))
+        table_host[n] = med
+        _log(f"profiled n={n} (pinned host): " + " ".join(f"{t * 1e3:.3f}" for t in med) + " ms")
+        del hu, ho
 
     def step(ev=None):
         chosen = {}
@@ -619,6 +706,36 @@ def main():
                      "per_launch_us": round(per_launch_ms * 1e3, 2)},
     }
     res["largest_size_pct_of_copy_probe"] = round(100.0 * res["largest_size_gbs"] / copy_gbs, 2)
+
+    def per_size(tab):
+        out = {}
+        for n in SIZES:
+            alg = 16.0 * n ** 3 * SWEEPS
+            g = [alg / t / 1e9 for t in tab[n]]
+            bg = max(range(5), key=lambda v: g[v])
+            bh = max(range(5, V), key=lambda v: g[v])
+            out[str(n)] = {"gbs_per_variant": [round(x, 2) for x in g],
+                           "best_gpu": bg, "best_gpu_gbs": round(g[bg], 2),
+                           "best_gpu_pct_peak": round(100.0 * g[bg] / HBM_PEAK_GBS, 2),
+                           "best_host": bh, "best_host_gbs": round(g[bh], 2),
+                           "gpu_over_host": round(g[bg] / g[bh], 3)}
+        return out
+
+    def crossover(tab):
+        """Smallest size from which the best GPU variant stays ahead of the best host one."""
+        first = None
+        for n in reversed(SIZES):
+            if min(tab[n][:5]) < min(tab[n][5:]):
+                first = n
+            else:
+                break
+        return first
+
+    res["per_size_device_resident"] = per_size(table)
+    res["per_size_pinned_host"] = per_size(table_host)
+    res["gpu_ahead_from_n"] = {"device_resident": crossover(table),
+                               "pinned_host": crossover(table_host)}
+    res["host"] = host_description()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)
