@@ -94,9 +94,10 @@ enum ao_family {
     AO_FAM_JACOBI_ZREG_T3 = 5, /* GPU: the same with three sweeps fused per pass; bx = 64,
                                   by (1|2|3|4|6|8) rows per wave, bz planes; S mod 3 sweeps
                                   run first as one single or one two-sweep pass */
-    AO_FAM_JACOBI_ZREG_T4 = 6, /* GPU: four sweeps fused per pass; bx = 64, by (1|2|3|4),
+    AO_FAM_JACOBI_ZREG_T4 = 6, /* GPU: four sweeps fused per pass; bx = 64, by (1..5),
                                   bz planes; S mod 4 sweeps run first as one single, two-
-                                  or three-sweep pass */
+                                  or three-sweep pass (each with the largest row count not
+                                  above by that its family takes) */
     AO_FAM_JACOBI_COSCHED = 7, /* host CPU + GPU together (target AO_TARGET_GPU): the first
                                   round(nz * bx / 10) z-planes sweep on the host (OpenMP,
                                   whole rows in tiles of 8), the rest on the GPU (register

@@ -166,6 +166,9 @@ bool t2_rows_ok(int r) {
            r == 16;
 }
 
+// rows per wave the three-sweep kernel is compiled for
+bool t3_rows_ok(int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 6 || r == 8; }
+
 int validate_variant(int kind, const ao_variant& v, int id) {
     const std::string at = "variant " + std::to_string(id) + ": ";
     if (kind == AO_JACOBI7_F64) {
@@ -185,10 +188,7 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL,
                         at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
-        if (v.family == AO_FAM_JACOBI_ZREG_T3 &&
-            (v.bx != 64 || !(v.by == 1 || v.by == 2 || v.by == 3 || v.by == 4 || v.by == 6 ||
-                             v.by == 8) ||
-             v.bz <= 0))
+        if (v.family == AO_FAM_JACOBI_ZREG_T3 && (v.bx != 64 || !t3_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1|2|3|4|6|8, bz > 0");
         if (v.family == AO_FAM_JACOBI_COSCHED) {
             if (v.bx < 0 || v.bx > 10 || v.by != 0 || v.bz != 0)
@@ -196,8 +196,8 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             return AO_OK;
         }
         if (v.family == AO_FAM_JACOBI_ZREG_T4 &&
-            (v.bx != 64 || v.by < 1 || v.by > 4 || v.bz <= 0))
-            return fail(AO_EINVAL, at + "four-sweep z-march needs bx 64, by 1..4, bz > 0");
+            (v.bx != 64 || v.by < 1 || v.by > 5 || v.bz <= 0))
+            return fail(AO_EINVAL, at + "four-sweep z-march needs bx 64, by 1..5, bz > 0");
         if (v.family == AO_FAM_JACOBI_ZREG &&
             ((v.bx != 64 && v.bx != 128) || (v.by != 1 && v.by != 2 && v.by != 4 && v.by != 8) ||
              v.bz <= 0))
@@ -523,13 +523,17 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
                                                               : 1;
             const int rem = S % P;
             const int L = S / P + (rem ? 1 : 0);
-            // (its rows per wave: the largest of 1|2|4|8 not above the variant's)
+            // (each with the largest row count per wave, not above the
+            // variant's, that its family is built for)
             const int single_rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
+            int two_rows = v.by, three_rows = v.by;
+            while (two_rows > 1 && !t2_rows_ok(two_rows)) --two_rows;
+            while (three_rows > 1 && !t3_rows_ok(three_rows)) --three_rows;
             const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, single_rows, v.bz,
                                     v.flags & AO_VF_NT_STORE};
-            const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, v.by, v.bz,
+            const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, two_rows, v.bz,
                                  v.flags & AO_VF_NT_STORE};
-            const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, v.by, v.bz,
+            const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, three_rows, v.bz,
                                    v.flags & AO_VF_NT_STORE};
             auto launch = [&](int l, const double* src, double* dst) {
                 if (P == 1) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
