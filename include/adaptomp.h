@@ -282,10 +282,12 @@ int batch_create(const ao_args* inst, int count, ao_batch** out);
 int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen);
 
 /* Run every instance once: one persistent kernel per pass over the work
- * list -- a pass is one sweep, or two sweeps on the fused tiles (the first
- * pass of an odd sweep count is then a single sweep), so an instance on a
- * fused tile takes ceil(S/2) passes.  Fused tiles run in a second
- * persistent kernel launched beside the first in each pass.  use_graph != 0
+ * list -- a pass is one sweep, two sweeps on the two-sweep tiles (the first
+ * pass of an odd sweep count is then a single sweep) or three on the
+ * three-sweep tiles (the first pass then takes the S mod 3 remaining
+ * sweeps), so an instance takes S, ceil(S/2) or ceil(S/3) passes.  The
+ * three tile families run in three persistent kernels launched one after
+ * the other in each pass.  use_graph != 0
  * launches all passes as one captured HIP graph (captured on first use,
  * re-captured after autotuning or batch_set_tiles).  Enqueued on
  * `stream`. */
@@ -293,14 +295,16 @@ int batch_run(ao_batch* b, void* stream, int use_graph);
 
 /* Per-bucket information: number of instances, work items and the tile
  * (tx, ty, tz) in use, 5 buckets each, any pointer may be NULL.  For a
- * fused tile tx = 62 (columns stored per 64-lane strip). */
+ * two-sweep tile tx = 62, for a three-sweep tile tx = 60 (columns stored
+ * per 64-lane strip). */
 int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz);
 
 /* The candidate tile table the autotuner searches: returns its length and,
  * when tiles is not NULL, writes (kind, tx, ty, tz) per candidate into
  * tiles[4 * length]; kind 0 = one point per thread, 1|2|4 = register
  * z-march with that many rows per wave, 11|12|14 = fused two-sweep
- * z-march with 1|2|4 rows per wave. */
+ * z-march with 1|2|4 rows per wave, 21|22|24 = fused three-sweep z-march
+ * with 1|2|4 rows per wave. */
 int batch_candidates(int* tiles);
 
 /* Fix the tile of each bucket: cand[5] candidate indices, -1 keeps the

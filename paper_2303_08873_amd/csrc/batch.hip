@@ -37,8 +37,13 @@ constexpr double kC = 0x1.5555555555555p-3;  // fl(1/6)
 constexpr int kThreads = 256;
 constexpr int kBuckets = 5;
 
-enum { kDirect = 0, kZreg1 = 1, kZreg2 = 2, kZreg4 = 4, kFused1 = 11, kFused2 = 12, kFused4 = 14 };
-__host__ __device__ constexpr bool is_fused(int kind) { return kind > 10; }
+enum {
+    kDirect = 0, kZreg1 = 1, kZreg2 = 2, kZreg4 = 4,      // one sweep per pass
+    kFused1 = 11, kFused2 = 12, kFused4 = 14,              // two sweeps per pass
+    kTri1 = 21, kTri2 = 22, kTri4 = 24                     // three sweeps per pass
+};
+__host__ __device__ constexpr bool is_fused(int kind) { return kind > 10 && kind < 20; }
+__host__ __device__ constexpr bool is_tri(int kind) { return kind > 20; }
 struct TileCfg {
     int kind, tx, ty, tz;
 };
@@ -50,6 +55,8 @@ constexpr TileCfg kCands[] = {
     {kZreg4, 64, 16, 24}, {kZreg4, 64, 16, 32}, {kZreg4, 64, 16, 64}, {kZreg2, 64, 8, 24},
     {kFused1, 62, 4, 16}, {kFused2, 62, 8, 16},  {kFused2, 62, 8, 32},  {kFused4, 62, 16, 16},
     {kFused4, 62, 16, 32}, {kFused1, 62, 4, 32},
+    {kTri1, 60, 4, 16},    {kTri2, 60, 8, 16},   {kTri4, 60, 16, 16},   {kTri4, 60, 16, 32},
+    {kTri2, 60, 8, 32},
 };
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 // default candidate per bucket before autotuning
@@ -67,10 +74,11 @@ struct Inst {
     int32_t nx, ny, nz, sweeps;
 };
 
-// launches an instance takes on a tile kind: one per sweep, or one per pair
-// of sweeps on fused tiles
+// launches an instance takes on a tile kind: one per sweep, one per pair of
+// sweeps on two-sweep tiles, one per three sweeps on three-sweep tiles (the
+// first pass then takes the S mod 3 remaining sweeps)
 __host__ __device__ inline int passes_of(int sweeps, int kind) {
-    return is_fused(kind) ? (sweeps + 1) / 2 : sweeps;
+    return is_tri(kind) ? (sweeps + 2) / 3 : is_fused(kind) ? (sweeps + 1) / 2 : sweeps;
 }
 
 __device__ __forceinline__ const double* src_of(const Inst& in, int s) {
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
         const Item it = items[w];
         const Inst in = insts[it.inst];
         const int P = passes_of(in.sweeps, kFused1);
-        if (pass >= P) continue;
+        if (pass >= P) continue;  // (the two-sweep kernel only sees two-sweep tiles)
         const TileCfg c = c_cands[it.cand];
         const double* src = pass == 0 ? in.u0 : (((P - pass) % 2 == 0) ? in.out : in.tmp);
         double* dst = ((P - 1 - pass) % 2 == 0) ? in.out : in.tmp;
@@ -233,6 +241,53 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
             else
                 zm::tb_column<2, 4, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
         }
+    }
+}
+
+// One pass of a three-sweep tile column: T = 1, 2 or 3 sweeps on lanes
+// 2 .. 61 of the strip starting at i0.
+template <int R>
+__device__ __forceinline__ void tri_column(int T, const double* src, double* dst, const Inst& in,
+                                           int i0, int j0, int z0, int k1) {
+    if (T == 1)
+        zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
+    else if (T == 2)
+        zm::tb_column<2, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
+    else
+        zm::tb_column<3, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
+}
+
+// Pass `pass` of every instance on a three-sweep tile: ping-pong over
+// ceil(S/3) passes so the last one lands in `out`; pass 0 takes the S mod 3
+// remaining sweeps when S is not a multiple of 3.  Strip x0 (a multiple of
+// 60) is computed on lanes x0-2 .. x0+61 and stored on x0 .. x0+59.
+__global__ __launch_bounds__(kThreads) void k_batch_fused3(const Inst* __restrict__ insts,
+                                                           const Item* __restrict__ items,
+                                                           int nitems, int pass) {
+    const int g = (int)gridDim.x;
+    const int slot = xcd_slot((int)blockIdx.x, g);
+    const int wave = (int)(threadIdx.x >> 6);
+    for (int w = slot; w < nitems; w += g) {
+        const Item it = items[w];
+        const Inst in = insts[it.inst];
+        const int P = passes_of(in.sweeps, kTri1);
+        if (pass >= P) continue;
+        const TileCfg c = c_cands[it.cand];
+        const double* src = pass == 0 ? in.u0 : (((P - pass) % 2 == 0) ? in.out : in.tmp);
+        double* dst = ((P - 1 - pass) % 2 == 0) ? in.out : in.tmp;
+        const int rem = in.sweeps % 3;
+        const int T = (pass == 0 && rem) ? rem : 3;
+        const int R = c.kind - 20;
+        const int j0 = it.y0 + wave * R;
+        if (j0 >= in.ny) continue;  // wave-uniform
+        const int k1 = min(in.nz, it.z0 + c.tz);
+        const int i0 = it.x0 - 2;
+        if (R == 1)
+            tri_column<1>(T, src, dst, in, i0, j0, it.z0, k1);
+        else if (R == 2)
+            tri_column<2>(T, src, dst, in, i0, j0, it.z0, k1);
+        else
+            tri_column<4>(T, src, dst, in, i0, j0, it.z0, k1);
     }
 }
 
@@ -263,9 +318,12 @@ struct ao_batch {
     Item* d_items = nullptr;   // single-sweep tiles (direct, zreg)
     int nitems = 0;
     int launches = 0;          // passes of the single-sweep tiles
-    Item* d_items_f = nullptr;  // fused tiles
+    Item* d_items_f = nullptr;  // two-sweep tiles
     int nitems_f = 0;
     int launches_f = 0;
+    Item* d_items_3 = nullptr;  // three-sweep tiles
+    int nitems_3 = 0;
+    int launches_3 = 0;
     int items_per_bucket[kBuckets] = {0};
     double* scratch = nullptr;
     int grid = 0;
@@ -279,6 +337,7 @@ struct ao_batch {
         if (cap_stream) hipStreamDestroy(cap_stream);
         if (d_items) hipFree(d_items);
         if (d_items_f) hipFree(d_items_f);
+        if (d_items_3) hipFree(d_items_3);
         if (d_insts) hipFree(d_insts);
         if (scratch) hipFree(scratch);
     }
@@ -320,15 +379,18 @@ hipError_t upload_list(Item** d, int* count, const std::vector<Item>& items) {
     return e;
 }
 
-// Splits the work list by kernel (single-sweep tiles / fused tiles) and
-// counts the launches each kernel needs.
+// Splits the work list by kernel (single-sweep / two-sweep / three-sweep
+// tiles) and counts the launches each kernel needs.
 hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
-    std::vector<Item> single, fused;
-    b->launches = b->launches_f = 0;
+    std::vector<Item> single, fused, tri;
+    b->launches = b->launches_f = b->launches_3 = 0;
     for (const Item& it : items) {
         const int kind = kCands[it.cand].kind;
         const int P = passes_of(b->insts[it.inst].sweeps, kind);
-        if (is_fused(kind)) {
+        if (is_tri(kind)) {
+            tri.push_back(it);
+            b->launches_3 = std::max(b->launches_3, P);
+        } else if (is_fused(kind)) {
             fused.push_back(it);
             b->launches_f = std::max(b->launches_f, P);
         } else {
@@ -338,6 +400,7 @@ hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
     }
     hipError_t e = upload_list(&b->d_items, &b->nitems, single);
     if (e == hipSuccess) e = upload_list(&b->d_items_f, &b->nitems_f, fused);
+    if (e == hipSuccess) e = upload_list(&b->d_items_3, &b->nitems_3, tri);
     return e;
 }
 
@@ -350,13 +413,18 @@ hipError_t launch_sweeps(ao_batch* b, hipStream_t s) {
         }
     }
     const int grid = std::min(b->nitems, b->grid), grid_f = std::min(b->nitems_f, b->grid);
-    for (int l = 0; l < std::max(b->launches, b->launches_f); ++l) {
+    const int grid_3 = std::min(b->nitems_3, b->grid);
+    const int L = std::max(b->launches, std::max(b->launches_f, b->launches_3));
+    for (int l = 0; l < L; ++l) {
         if (l < b->launches && b->nitems > 0)
             hipLaunchKernelGGL(k_batch_sweep, dim3(grid), dim3(kThreads), 0, s, b->d_insts,
                                b->d_items, b->nitems, l);
         if (l < b->launches_f && b->nitems_f > 0)
             hipLaunchKernelGGL(k_batch_fused, dim3(grid_f), dim3(kThreads), 0, s, b->d_insts,
                                b->d_items_f, b->nitems_f, l);
+        if (l < b->launches_3 && b->nitems_3 > 0)
+            hipLaunchKernelGGL(k_batch_fused3, dim3(grid_3), dim3(kThreads), 0, s, b->d_insts,
+                               b->d_items_3, b->nitems_3, l);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -91,8 +91,9 @@ def test_batch_256_uneven_graph_and_autotune(env):
 
 
 def test_every_tile_candidate_bit_identical(env, orc):
-    # every tile of the autotuner's table (single-sweep and fused two-sweep)
-    # forced on every bucket: instances of all sizes, sweep counts 0..7
+    # every tile of the autotuner's table (single-sweep, fused two- and
+    # three-sweep) forced on every bucket: instances of all sizes, sweep
+    # counts 0..7 (every remainder of the fused passes)
     ao, torch, dev, st = env
     shapes = [(8, 8, 8), (5, 17, 3), (70, 9, 40), (1, 1, 30), (33, 65, 2), (130, 20, 11),
               (16, 16, 16), (3, 200, 4), (63, 62, 5), (125, 7, 64), (62, 1, 1), (124, 33, 9)]

@@ -202,11 +202,14 @@ def test_batch_candidate_table_and_tile_errors(ao):
     cands = ao.batch_candidates()
     assert len(cands) == ao.lib.batch_candidates(None) >= 16
     for kind, tx, ty, tz in cands:
-        assert kind in (0, 1, 2, 4, 11, 12, 14) and tz >= 1
+        assert kind in (0, 1, 2, 4, 11, 12, 14, 21, 22, 24) and tz >= 1
         if kind in (1, 2, 4):
             assert (tx, ty) == (64, 4 * kind)
-        if kind > 10:
+        if 10 < kind < 20:
             assert (tx, ty) == (62, 4 * (kind - 10))
+        if kind > 20:
+            assert (tx, ty) == (60, 4 * (kind - 20))
+    assert {k for k, *_ in cands} >= {0, 1, 11, 21}
     with pytest.raises(ao.AdaptError):
         ao.batch_set_tiles(None, [0] * 5)
 
