@@ -245,16 +245,25 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
 }
 
 // One pass of a three-sweep tile column: T = 1, 2 or 3 sweeps on lanes
-// 2 .. 61 of the strip starting at i0.
+// 2 .. 61 of the strip starting at i0; three-sweep passes of waves whose
+// columns and rows (with the 3-row halo) lie inside the grid take the march
+// without per-lane selects.
 template <int R>
 __device__ __forceinline__ void tri_column(int T, const double* src, double* dst, const Inst& in,
                                            int i0, int j0, int z0, int k1) {
-    if (T == 1)
+    if (T == 1) {
         zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
-    else if (T == 2)
+    } else if (T == 2) {
         zm::tb_column<2, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
-    else
-        zm::tb_column<3, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
+    } else {
+        const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 3 && j0 + R + 3 <= in.ny;
+        if (inner)
+            zm::tb_column<3, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
+                                                           k1, 2, 61);
+        else
+            zm::tb_column<3, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1,
+                                                     2, 61);
+    }
 }
 
 // Pass `pass` of every instance on a three-sweep tile: ping-pong over
