@@ -114,8 +114,9 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // T sweeps of src on the wave's column: lanes hold x = i0 + lane, output
 // rows j0 .. j0+R-1 (j0 < ny), output planes [k0, k1); level T is stored on
 // lanes lane_lo .. lane_hi that lie inside the grid (the caller keeps that
-// window within T-1 .. 64-T).  Every load is bounds-checked; the whole wave
-// must call this (cross-lane moves).  EARLY: the next plane's level-0 rows
+// window within T-1 .. 64-T).  Every load stays inside the grid (masked,
+// or at clamped coordinates); the whole wave must call this (cross-lane
+// moves).  EARLY: the next plane's level-0 rows
 // and strip edges are loaded as soon as level 1 has consumed this plane's
 // (into the same registers), so they are in flight while levels 2..T
 // compute instead of at the top of the next iteration; level T is then
