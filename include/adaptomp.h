@@ -92,7 +92,7 @@ enum ao_family {
                                   rows per wave, bz planes; an odd sweep count adds one
                                   single sweep */
     AO_FAM_JACOBI_ZREG_T3 = 5, /* GPU: the same with three sweeps fused per pass; bx = 64,
-                                  by (1|2|3|4|6|8) rows per wave, bz planes; S mod 3 sweeps
+                                  by (1..6|8) rows per wave, bz planes; S mod 3 sweeps
                                   run first as one single or one two-sweep pass */
     AO_FAM_JACOBI_ZREG_T4 = 6, /* GPU: four sweeps fused per pass; bx = 64, by (1..5),
                                   bz planes; S mod 4 sweeps run first as one single, two-

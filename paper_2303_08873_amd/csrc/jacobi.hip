@@ -626,7 +626,7 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
 #define AO_TB(TT, RR)                                                                          \
     if (T == TT && R == RR)                                                                    \
         return launch_zreg_tb<TT, RR>(nt, pf, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
-    AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 6) AO_TB(3, 8)
+    AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 5) AO_TB(3, 6) AO_TB(3, 8)
     AO_TB(4, 1) AO_TB(4, 2) AO_TB(4, 3) AO_TB(4, 4) AO_TB(4, 5)
 #undef AO_TB
     return hipErrorInvalidConfiguration;

@@ -167,7 +167,7 @@ bool t2_rows_ok(int r) {
 }
 
 // rows per wave the three-sweep kernel is compiled for
-bool t3_rows_ok(int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 6 || r == 8; }
+bool t3_rows_ok(int r) { return (r >= 1 && r <= 6) || r == 8; }
 
 int validate_variant(int kind, const ao_variant& v, int id) {
     const std::string at = "variant " + std::to_string(id) + ": ";
@@ -189,7 +189,7 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             return fail(AO_EINVAL,
                         at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
         if (v.family == AO_FAM_JACOBI_ZREG_T3 && (v.bx != 64 || !t3_rows_ok(v.by) || v.bz <= 0))
-            return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1|2|3|4|6|8, bz > 0");
+            return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1..6|8, bz > 0");
         if (v.family == AO_FAM_JACOBI_COSCHED) {
             if (v.bx < 0 || v.bx > 10 || v.by != 0 || v.bz != 0)
                 return fail(AO_EINVAL, at + "co-scheduling needs bx 0..10 (host tenths), by = bz = 0");

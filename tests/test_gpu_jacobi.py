@@ -186,12 +186,12 @@ def test_two_sweep_family_all_shapes(env, orc, shape, S):
 
 
 T3 = [(1, 1, 0), (1, 5, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2, 0), (4, 16, 1),
-      (6, 9, 0), (6, 1, 1), (8, 4, 0), (8, 32, 1)]
+      (6, 9, 0), (6, 1, 1), (8, 4, 0), (5, 11, 1)]
 T4 = [(1, 1, 0), (1, 6, 1), (2, 3, 0), (2, 16, 1), (3, 7, 0), (3, 32, 1), (4, 2, 0), (4, 16, 1),
       (4, 5, 1), (2, 1, 0), (5, 3, 0), (5, 64, 1)]
 # the same families with the early next-plane loads (flag 2, with and without
 # streaming stores)
-T3_PF = [(1, 1, 2), (1, 5, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4, 2, 2),
+T3_PF = [(1, 1, 2), (1, 5, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (5, 32, 3), (4, 2, 2),
          (4, 16, 3), (6, 9, 2), (6, 1, 3), (8, 4, 2), (8, 32, 3)]
 T4_PF = [(1, 1, 2), (1, 6, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4, 2, 2),
          (4, 16, 3), (4, 5, 3), (2, 1, 2), (5, 9, 2), (5, 64, 3)]
