@@ -202,6 +202,26 @@ __global__ __launch_bounds__(kThreads) void k_batch_sweep(const Inst* __restrict
     }
 }
 
+// One pass of a two-sweep tile column: one sweep (single) or two on lanes
+// 1 .. 62 of the strip starting at i0; two-sweep passes of waves whose
+// columns and rows (with the 2-row halo) lie inside the grid take the march
+// without per-lane selects.
+template <int R>
+__device__ __forceinline__ void pair_column(bool single, const double* src, double* dst,
+                                            const Inst& in, int i0, int j0, int z0, int k1) {
+    if (single) {
+        zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 1, 62);
+    } else {
+        const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 2 && j0 + R + 2 <= in.ny;
+        if (inner)
+            zm::tb_column<2, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
+                                                           k1, 1, 62);
+        else
+            zm::tb_column<2, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1,
+                                                     1, 62);
+    }
+}
+
 // Pass `pass` of every instance on a fused tile: ping-pong over ceil(S/2)
 // passes so the last one lands in `out`; pass 0 is a single sweep when S is
 // odd.  Strip x0 (a multiple of 62) is computed on lanes x0-1 .. x0+62.
@@ -225,36 +245,32 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
         if (j0 >= in.ny) continue;  // wave-uniform
         const int k1 = min(in.nz, it.z0 + c.tz);
         const int i0 = it.x0 - 1;
-        if (R == 1) {
-            if (single)
-                zm::tb_column<1, 1, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-            else
-                zm::tb_column<2, 1, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-        } else if (R == 2) {
-            if (single)
-                zm::tb_column<1, 2, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-            else
-                zm::tb_column<2, 2, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-        } else {
-            if (single)
-                zm::tb_column<1, 4, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-            else
-                zm::tb_column<2, 4, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, it.z0, k1, 1, 62);
-        }
+        if (R == 1)
+            pair_column<1>(single, src, dst, in, i0, j0, it.z0, k1);
+        else if (R == 2)
+            pair_column<2>(single, src, dst, in, i0, j0, it.z0, k1);
+        else
+            pair_column<4>(single, src, dst, in, i0, j0, it.z0, k1);
     }
 }
 
 // One pass of a three-sweep tile column: T = 1, 2 or 3 sweeps on lanes
-// 2 .. 61 of the strip starting at i0; three-sweep passes of waves whose
-// columns and rows (with the 3-row halo) lie inside the grid take the march
-// without per-lane selects.
+// 2 .. 61 of the strip starting at i0; two- and three-sweep passes of waves
+// whose columns and rows (with the T-row halo) lie inside the grid take the
+// march without per-lane selects.
 template <int R>
 __device__ __forceinline__ void tri_column(int T, const double* src, double* dst, const Inst& in,
                                            int i0, int j0, int z0, int k1) {
     if (T == 1) {
         zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
     } else if (T == 2) {
-        zm::tb_column<2, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
+        const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 2 && j0 + R + 2 <= in.ny;
+        if (inner)
+            zm::tb_column<2, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
+                                                           k1, 2, 61);
+        else
+            zm::tb_column<2, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1,
+                                                     2, 61);
     } else {
         const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 3 && j0 + R + 3 <= in.ny;
         if (inner)
