@@ -56,6 +56,16 @@ def cpu_baseline(repeats=2):
                       f"({dt:.1f} s)"}
 
 
+def oracle_timing(fn, work_bytes, sample):
+    """A cpu_baseline object: the oracle call `fn` timed once on the host (one
+    core), rated by the algorithmic bytes of the work it did."""
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return {"value": round(work_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} ({dt:.1f} s)"}
+
+
 def host_description():
     """Host threads and CPU model for the host-variant rows."""
     model = None
@@ -182,7 +192,7 @@ def kernel_only(variant: int, launches: int = 3):
                       "copies": 5, "copy_bytes_each": 16 * n ** 3}), flush=True)
 
 
-def batch_workload(steps: int, warmup: int):
+def batch_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     """256 uneven FP64 Jacobi grids (each dim log-uniform in [8, 256], seed 3),
     5 sweeps each: per-instance region runs vs one persistent launch per
     sweep (eager) vs the captured graph, after autotuning the tile per
@@ -252,10 +262,21 @@ def batch_workload(steps: int, warmup: int):
            "autotune_seconds": round(tune_s, 3), "autotuned_candidates": chosen,
            "bucket_instances": inst, "bucket_items": items, "bucket_tiles": tiles}
     ao.batch_destroy(b)
+    res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
+                       "traffic": None,
+                       "kernel": "the captured graph (persistent batch kernels, all passes)"}
+    if not no_cpu_baseline:
+        import oracle
+        hosts = [(u0.cpu().numpy(), int(nx), int(ny), int(nz))
+                 for (u0, _), (nx, ny, nz) in zip(bufs, shapes)]
+        res["cpu_baseline"] = oracle_timing(
+            lambda: [oracle.jacobi7(h, nx, ny, nz, S) for h, nx, ny, nz in hosts], total,
+            "serial C oracle, every grid of the batch x 5 sweeps once")
     print(json.dumps(res), flush=True)
 
 
-def spmv_workload(steps: int, warmup: int):
+def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     """FP64 CSR SpMV region, n = 2^22 rows, Pareto-tail rows (index 1.5, mean
     16, max 4096), seed 5; 9 variants {thread-row, wave-row, merge-path} x
     {64, 256, 1024}.  The cost model is trained on profiled matrices of other
@@ -334,10 +355,21 @@ def spmv_workload(steps: int, warmup: int):
            "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
            "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
            "held_out": rows}
+    v = ao.spmv_variants()[chosen]
+    res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
+                       "traffic": None,
+                       "kernel": f"variant {chosen} (family={v.family} bx={v.bx} by={v.by}) at n=2^22"}
+    if not no_cpu_baseline:
+        import oracle
+        h = {k: t[k].cpu().numpy() for k in ("row_ptr", "col", "val", "x")}
+        res["cpu_baseline"] = oracle_timing(
+            lambda: oracle.spmv_canonical(h["row_ptr"], h["col"], h["val"], h["x"]), byt,
+            "serial C oracle, one SpMV of the 2^22 matrix in the canonical order")
     print(json.dumps(res), flush=True)
 
 
-def relax_workload(steps: int, warmup: int):
+def relax_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     """Weighted Jacobi relaxation region (the AMGMk relax kernel): n = 2^22
     rows of the Pareto-row matrix (tail 1.5, mean 16, max 4096, seed 5) with
     a strictly dominant diagonal, omega = 2/3, 10 sweeps per execution; the
@@ -425,6 +457,17 @@ def relax_workload(steps: int, warmup: int):
            "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
            "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
            "held_out": rows}
+    v = ao.spmv_variants()[chosen]
+    res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
+                       "traffic": None,
+                       "kernel": f"variant {chosen} (family={v.family} bx={v.bx} by={v.by}) at n=2^22"}
+    if not no_cpu_baseline:
+        import oracle
+        h = {k: t[k].cpu().numpy() for k in ("row_ptr", "col", "val", "x", "b", "d")}
+        res["cpu_baseline"] = oracle_timing(
+            lambda: oracle.relax(h["row_ptr"], h["col"], h["val"], h["x"], h["b"], h["d"], omega, 2),
+            byt * 2 // S, "serial C oracle, 2 of the 10 sweeps on the 2^22 system")
     print(json.dumps(res), flush=True)
 
 
@@ -549,13 +592,13 @@ def main():
             kernel_only(args.kernel_only)
         return
     if args.workload == "batch":
-        batch_workload(args.steps, args.warmup)
+        batch_workload(args.steps, args.warmup, args.no_cpu_baseline)
         return
     if args.workload == "spmv":
-        spmv_workload(args.steps, args.warmup)
+        spmv_workload(args.steps, args.warmup, args.no_cpu_baseline)
         return
     if args.workload == "relax":
-        relax_workload(args.steps, args.warmup)
+        relax_workload(args.steps, args.warmup, args.no_cpu_baseline)
         return
     if args.workload == "cosched":
         cosched_workload(args.steps, args.warmup)
