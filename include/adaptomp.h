@@ -122,6 +122,10 @@ enum ao_family {
                                  three and four, as soon as the first fused sweep has
                                  consumed the current plane) */
 #define AO_VF_OCCUPANCY 4     /* two-sweep z-march: registers capped for 4 waves per SIMD */
+#define AO_VF_STAGED 8        /* three- and four-sweep z-marches (not with
+                                 AO_VF_HALO_PREFETCH): waves inside the grid receive
+                                 level 0 through asynchronous global->LDS copies one
+                                 plane ahead (about 57 KB of LDS per block) */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,

@@ -12,7 +12,8 @@ from __future__ import annotations
 from ._lib import (  # noqa: F401
     AO_CSR_RELAX_F64, AO_CSR_SPMV_F64, AO_JACOBI7_F64, AO_MAX_FEATURES, AO_MAX_VARIANTS, AO_MLP_PARAMS,
     AO_OK, AO_NOTE_FALLBACK, AO_NOTE_UNTRAINED, AO_PROFILE_RECORD, AO_TARGET_GPU,
-    AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_OCCUPANCY, FAM_JACOBI_DIRECT,
+    AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_OCCUPANCY, AO_VF_STAGED,
+    FAM_JACOBI_DIRECT,
     FAM_JACOBI_HOST, FAM_JACOBI_ZMARCH, FAM_JACOBI_ZREG, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
     FAM_JACOBI_ZREG_T4, FAM_JACOBI_COSCHED,
     FAM_SPMV_BANDED, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, AdaptError, Args, Stats,

@@ -407,8 +407,9 @@ void jac_zreg_t2_occ(const double* __restrict__ src, double* __restrict__ dst, i
 // T sweeps per pass (temporal blocking factor T >= 2), the two-sweep scheme
 // generalised: one wave runs tb_column (zmarch.h) on its 64-lane strip,
 // starting at i0 = (66 - 2T)*bi - (T - 1), storing lanes T-1 .. 64-T.  PF
-// selects the march's early next-plane loads.
-template <int T, int R, bool NT, bool PF>
+// selects the march's early next-plane loads, ST the staged (global->LDS)
+// level 0 for waves inside the grid.
+template <int T, int R, bool NT, bool PF, bool ST>
 __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
                                              double* __restrict__ dst, int nx, int ny, int nz,
                                              int nbx, int nby, int bz, unsigned nblocks) {
@@ -426,6 +427,13 @@ __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
     // every column (with the strip-edge loads) and row (with the T-row halo)
     // the wave touches inside the grid: the march without per-lane selects
     const bool inner = i0 >= 1 && i0 + 64 < nx && j0 >= T && j0 + R + T <= ny;  // wave-uniform
+    if constexpr (ST && !PF) {
+        if (inner && i0 >= 2 && i0 + 66 <= nx && (size_t)nx * (size_t)ny * 8u < ((size_t)1 << 32)) {
+            zm::tb_column<T, R, NT, false, true, true, true>(src, dst, nx, ny, nz, i0, j0, k0,
+                                                             min(nz, k0 + bz), T - 1, 64 - T);
+            return;
+        }
+    }
     if (inner)
         zm::tb_column<T, R, NT, PF, true, true>(src, dst, nx, ny, nz, i0, j0, k0, min(nz, k0 + bz),
                                                 T - 1, 64 - T);
@@ -434,31 +442,37 @@ __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
                                     64 - T);
 }
 
-template <int T, int R, bool NT, bool PF>
+template <int T, int R, bool NT, bool PF, bool ST>
 __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg_tb(const double* __restrict__ src,
                                                                 double* __restrict__ dst, int nx,
                                                                 int ny, int nz, int nbx, int nby,
                                                                 int bz, unsigned nblocks) {
-    zreg_tb_body<T, R, NT, PF>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
+    zreg_tb_body<T, R, NT, PF, ST>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
 }
 
 template <int T, int R>
-hipError_t launch_zreg_tb(bool nt, bool pf, dim3 grid, hipStream_t s, const double* src,
+hipError_t launch_zreg_tb(bool nt, bool pf, bool st, dim3 grid, hipStream_t s, const double* src,
                           double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
                           unsigned nb) {
     const dim3 block(64 * kZregWaves);
-    if (nt && pf)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, true>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
+    if (st && nt)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false, true>), grid, block, 0, s, src, dst, nx,
+                           ny, nz, nbx, nby, bz, nb);
+    else if (st)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false, true>), grid, block, 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
+    else if (nt && pf)
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, true, false>), grid, block, 0, s, src, dst, nx,
+                           ny, nz, nbx, nby, bz, nb);
     else if (nt)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false, false>), grid, block, 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
     else if (pf)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, true>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, true, false>), grid, block, 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
     else
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
+        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false, false>), grid, block, 0, s, src, dst,
+                           nx, ny, nz, nbx, nby, bz, nb);
     return hipGetLastError();
 }
 
@@ -618,6 +632,8 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
     if (T == 0 || v.bx != 64 || bz <= 0 || nx > (1 << 28)) return hipErrorInvalidConfiguration;
     const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
     const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
+    const bool st = (v.flags & AO_VF_STAGED) != 0;
+    if (st && pf) return hipErrorInvalidConfiguration;
     const int nbx = cdiv(nx, 66 - 2 * T), nby = cdiv(ny, kZregWaves * R);
     const int64_t nb = (int64_t)nbx * nby * cdiv(nz, bz);
     if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -625,7 +641,7 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
     const unsigned u = (unsigned)nb;
 #define AO_TB(TT, RR)                                                                          \
     if (T == TT && R == RR)                                                                    \
-        return launch_zreg_tb<TT, RR>(nt, pf, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
+        return launch_zreg_tb<TT, RR>(nt, pf, st, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
     AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 5) AO_TB(3, 6) AO_TB(3, 8)
     AO_TB(4, 1) AO_TB(4, 2) AO_TB(4, 3) AO_TB(4, 4) AO_TB(4, 5)
 #undef AO_TB

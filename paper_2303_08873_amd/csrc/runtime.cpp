@@ -188,6 +188,11 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL,
                         at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
+        if ((v.flags & AO_VF_STAGED) &&
+            ((v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4) ||
+             (v.flags & AO_VF_HALO_PREFETCH)))
+            return fail(AO_EINVAL, at + "staged level 0 is for the three- and four-sweep "
+                                        "z-marches, without the prefetch flag");
         if (v.family == AO_FAM_JACOBI_ZREG_T3 && (v.bx != 64 || !t3_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL, at + "three-sweep z-march needs bx 64, by 1..6|8, bz > 0");
         if (v.family == AO_FAM_JACOBI_COSCHED) {

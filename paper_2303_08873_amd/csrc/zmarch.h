@@ -126,8 +126,12 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // indices are wave-uniform (the caller's j0 comes from wave_index()), so
 // loads go to clamped rows through scalar row bases; otherwise rows are
 // per-lane values and out-of-grid loads are masked (fewer scalar registers,
-// for kernels that inline several marches).
-template <int T, int R, bool NT, bool EARLY = false, bool SROW = true, bool INNER = false>
+// for kernels that inline several marches).  STAGE (with INNER, without
+// EARLY): level 0 arrives through asynchronous global->LDS copies one plane
+// ahead (see the staged loop below); the caller then also keeps columns
+// i0-2 .. i0+65 inside the grid and the plane below 2^32 bytes.
+template <int T, int R, bool NT, bool EARLY = false, bool SROW = true, bool INNER = false,
+          bool STAGE = false>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
                                           int lane_lo, int lane_hi) {
@@ -225,6 +229,86 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
             tb_rotate<T, R, 1>(below, centre, fresh);
         }
         store_hold();
+        return;
+    }
+    if constexpr (INNER && STAGE && !EARLY) {
+        // Staged level 0: every plane's level-0 rows (x = i0-2 .. i0+65, so
+        // the strip edges too) are copied global->LDS by 16-byte pieces into
+        // one of two per-wave buffers, one plane ahead, so the copies hold no
+        // registers and are in flight while a whole plane computes.  The
+        // copies are inline assembly with their waits written out: at the
+        // top of each iteration vmcnt(0) covers the copy of plane k+1 issued
+        // in the previous iteration and the stores issued just before it
+        // (level T is stored one iteration late, ahead of the copy, so the
+        // copy is always the youngest memory operation); lgkmcnt(0) before a
+        // buffer is refilled drains the reads of its previous plane; a last
+        // vmcnt(0) leaves no copy writing LDS when the wave ends.
+        constexpr int kRowB = 68 * 8;                // one staged row
+        constexpr int kPieces = S::nl(0) * 34;       // 16-byte pieces per plane
+        constexpr int kCopies = (kPieces + 63) / 64;  // copy instructions per plane
+        constexpr int kBuf = kCopies * 1024;         // bytes per plane buffer
+        __shared__ __attribute__((aligned(16))) char stg[4 * 2 * kBuf];
+        const int wv = wave_index();
+        char* mine = stg + wv * 2 * kBuf;
+        const unsigned lds0 =
+            (unsigned)(uintptr_t)((__attribute__((address_space(3))) char*)mine);
+        unsigned poff[kCopies];  // lane's byte offset within a plane, per copy
+#pragma unroll
+        for (int p = 0; p < kCopies; ++p) {
+            const int g = p * 64 + lane;
+            const int r = min(g / 34, S::nl(0) - 1), c = min(g - r * 34, 33);
+            poff[p] = (unsigned)(((size_t)(j0 - T + r) * nx + (size_t)(i0 - 2 + 2 * c)) * 8u);
+        }
+        auto stage = [&](int kp) {  // plane kp (clamped into the grid) -> buffer kp & 1
+            const char* pb = (const char*)(src + (size_t)min(max(kp, 0), nz - 1) * plane);
+            const unsigned m0 = lds0 + (unsigned)((kp & 1) * kBuf);
+#pragma unroll
+            for (int p = 0; p < kCopies; ++p)
+                // (one wait state between the M0 write and the copy that reads it)
+                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :
+                             : "s"(m0 + (unsigned)(p * 1024)), "v"((const void*)(pb + poff[p]))
+                             : "memory", "m0");
+        };
+        // lane's x offset in a staged row: its own point, or (strip edges)
+        // x = i0-1 on lane 0 and x = i0+64 on lane 63
+        const int xo = (lane + 2) * 8;
+        const int eo = lane == 0 ? 8 : lane == 63 ? 66 * 8 : xo;
+        auto rd = [&](int kp, int q, int off) -> double {
+            return *(const double*)(mine + (kp & 1) * kBuf + q * kRowB + off);
+        };
+        const int kend = k1 + T - 2;
+        double hold[R];
+        int hold_p = -1;
+        auto store_hold = [&]() {
+            if (hold_p >= k0 && hold_p < k1) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    if (lane_out)
+                        put<NT>(dst + (size_t)hold_p * plane + (size_t)(j0 + q) * nx + i, hold[q]);
+            }
+        };
+        stage(ka);
+        stage(ka + 1);
+        for (int k = ka; k <= kend; ++k) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            double ex[S::nl(1)];
+#pragma unroll
+            for (int q = 0; q < S::nl(0); ++q) fresh[q] = rd(k + 1, q, xo);
+#pragma unroll
+            for (int q = 0; q < S::nl(1); ++q) ex[q] = rd(k, q + 1, eo);
+            zero_out(k + 1, fresh, S::nl(0));
+            zero_out(k, ex, S::nl(1));
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            store_hold();
+            if (k < kend) stage(k + 2);  // wave-uniform; refills plane k's buffer
+            tb_level<T, R, 1, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0,
+                                            k1, plane, lane, i, xin, lane_out, hold);
+            hold_p = k - T + 1;
+            tb_rotate<T, R, 0>(below, centre, fresh);
+        }
+        store_hold();
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         return;
     }
     for (int k = ka; k <= k1 + T - 2; ++k) {

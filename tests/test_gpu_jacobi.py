@@ -195,6 +195,12 @@ T3_PF = [(1, 1, 2), (1, 5, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (5, 32, 3), (4,
          (4, 16, 3), (6, 9, 2), (6, 1, 3), (8, 4, 2), (8, 32, 3)]
 T4_PF = [(1, 1, 2), (1, 6, 3), (2, 3, 2), (2, 16, 3), (3, 7, 2), (3, 32, 3), (4, 2, 2),
          (4, 16, 3), (4, 5, 3), (2, 1, 2), (5, 9, 2), (5, 64, 3)]
+# level 0 staged through LDS for waves inside the grid (flag 8, with and
+# without streaming stores)
+T3_ST = [(1, 1, 8), (1, 5, 9), (2, 3, 8), (2, 16, 9), (3, 7, 8), (4, 2, 9), (4, 16, 8),
+         (5, 11, 9), (6, 9, 8), (6, 1, 9), (8, 4, 8), (8, 32, 9)]
+T4_ST = [(1, 1, 8), (1, 6, 9), (2, 3, 8), (2, 16, 9), (3, 7, 8), (3, 32, 9), (4, 2, 8),
+         (4, 16, 9), (5, 5, 9), (5, 64, 9), (5, 3, 8), (2, 1, 8)]
 
 
 @pytest.mark.parametrize("shape,S", [((130, 37, 11), 3), ((1, 1, 9), 2), ((2, 33, 5), 4),
@@ -214,7 +220,9 @@ def test_three_and_four_sweep_families_all_shapes(env, orc, shape, S):
     out = torch.empty_like(u0)
     for tag, fam, lst in (("", ao.FAM_JACOBI_ZREG_T3, T3), ("", ao.FAM_JACOBI_ZREG_T4, T4),
                           ("pf", ao.FAM_JACOBI_ZREG_T3, T3_PF),
-                          ("pf", ao.FAM_JACOBI_ZREG_T4, T4_PF)):
+                          ("pf", ao.FAM_JACOBI_ZREG_T4, T4_PF),
+                          ("st", ao.FAM_JACOBI_ZREG_T3, T3_ST),
+                          ("st", ao.FAM_JACOBI_ZREG_T4, T4_ST)):
         vs = [ao.Variant(ao.AO_TARGET_GPU, fam, 64, r, bz, fl) for r, bz, fl in lst]
         h = ao.region_declare_variants(f"gpu_tb{tag}{fam}_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64,
                                        vs, model_type="roundrobin")

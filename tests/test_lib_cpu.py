@@ -137,6 +137,14 @@ def test_argument_errors(ao):
     ao.region_destroy(ao.region_declare_variants("t3rows", ao.AO_JACOBI7_F64, ok))
     ok = [ao.Variant(G, ao.FAM_JACOBI_ZREG_T4, 64, r, 8, 1) for r in (1, 2, 3, 4, 5)]
     ao.region_destroy(ao.region_declare_variants("t4rows", ao.AO_JACOBI7_F64, ok))
+    ok = [ao.Variant(G, fam, 64, 4, 16, fl) for fam in (ao.FAM_JACOBI_ZREG_T3, ao.FAM_JACOBI_ZREG_T4)
+          for fl in (ao.AO_VF_STAGED, ao.AO_VF_STAGED | ao.AO_VF_NT_STORE)]
+    ao.region_destroy(ao.region_declare_variants("staged_ok", ao.AO_JACOBI7_F64, ok))
+    for fam, fl in ((ao.FAM_JACOBI_ZREG_T2, ao.AO_VF_STAGED), (ao.FAM_JACOBI_ZREG, ao.AO_VF_STAGED),
+                    (ao.FAM_JACOBI_ZREG_T4, ao.AO_VF_STAGED | ao.AO_VF_HALO_PREFETCH)):
+        with pytest.raises(ao.AdaptError):  # staging only for the three- and four-sweep marches
+            ao.region_declare_variants(f"staged_bad_{fam}_{fl}", ao.AO_JACOBI7_F64,
+                                       [ao.Variant(G, fam, 64, 4, 16, fl)])
     ok = [ao.Variant(G, ao.FAM_JACOBI_COSCHED, f, 0, 0, 0) for f in range(11)]
     ao.region_destroy(ao.region_declare_variants("cosched_ok", ao.AO_JACOBI7_F64, ok))
     for bad in ((11, 0, 0), (-1, 0, 0), (5, 1, 0), (5, 0, 2)):
