@@ -123,9 +123,12 @@ enum ao_family {
                                  consumed the current plane) */
 #define AO_VF_OCCUPANCY 4     /* two-sweep z-march: registers capped for 4 waves per SIMD */
 #define AO_VF_STAGED 8        /* three- and four-sweep z-marches (not with
-                                 AO_VF_HALO_PREFETCH): waves inside the grid receive
-                                 level 0 through asynchronous global->LDS copies one
-                                 plane ahead (about 57 KB of LDS per block) */
+                                 AO_VF_HALO_PREFETCH): waves receive level 0 through
+                                 asynchronous global->LDS copies one plane ahead (32-64
+                                 KB of LDS per block); with more than 4 rows per wave
+                                 (four sweeps) or 6 (three) only waves inside the grid,
+                                 and for odd nx only waves whose 68 staged columns lie
+                                 inside it */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,

@@ -428,10 +428,26 @@ __device__ __forceinline__ void zreg_tb_body(const double* __restrict__ src,
     // the wave touches inside the grid: the march without per-lane selects
     const bool inner = i0 >= 1 && i0 + 64 < nx && j0 >= T && j0 + R + T <= ny;  // wave-uniform
     if constexpr (ST && !PF) {
-        if (inner && i0 >= 2 && i0 + 66 <= nx && (size_t)nx * (size_t)ny * 8u < ((size_t)1 << 32)) {
+        // staged level 0: columns x0 .. x0+67 from the even x0 = i0-2 or i0-3
+        const int x0 = i0 - 2 - (i0 & 1);
+        const bool fits = nx >= 2 && (size_t)nx * (size_t)ny * 8u < ((size_t)1 << 32) &&
+                          (!(nx & 1) || x0 + 68 <= nx);  // wave-uniform
+        // boundary waves stage too where the extra selects still fit two
+        // waves per SIMD (up to 4 rows per wave for four sweeps, 6 for three)
+        constexpr bool kEdges = (T == 4 && R <= 4) || (T == 3 && R <= 6);
+        __shared__ __attribute__((aligned(16))) char stg[zm::stage_lds_bytes<T, R>()];
+        if (fits && inner && x0 >= 0 && x0 + 68 <= nx) {
             zm::tb_column<T, R, NT, false, true, true, true>(src, dst, nx, ny, nz, i0, j0, k0,
-                                                             min(nz, k0 + bz), T - 1, 64 - T);
+                                                             min(nz, k0 + bz), T - 1, 64 - T, stg);
             return;
+        }
+        if constexpr (kEdges) {
+            if (fits) {
+                zm::tb_column<T, R, NT, false, true, false, true>(src, dst, nx, ny, nz, i0, j0, k0,
+                                                                  min(nz, k0 + bz), T - 1, 64 - T,
+                                                                  stg);
+                return;
+            }
         }
     }
     if (inner)

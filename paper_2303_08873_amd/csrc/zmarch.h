@@ -35,6 +35,13 @@ __device__ __forceinline__ void put(double* p, double v) {
 }
 
 template <int T, int R>
+struct TbShape;
+// LDS bytes a block of 4 waves needs for the staged level 0 (two plane
+// buffers of 16-byte pieces per wave, 34 pieces per staged row)
+template <int T, int R>
+constexpr int stage_lds_bytes() { return 4 * 2 * (((R + 2 * T) * 34 + 63) / 64) * 1024; }
+
+template <int T, int R>
 struct TbShape {
     static constexpr int nl(int l) { return R + 2 * (T - l); }
     // offset of level l in the packed centre / fresh arrays: sum of nl(0..l-1)
@@ -126,15 +133,16 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // indices are wave-uniform (the caller's j0 comes from wave_index()), so
 // loads go to clamped rows through scalar row bases; otherwise rows are
 // per-lane values and out-of-grid loads are masked (fewer scalar registers,
-// for kernels that inline several marches).  STAGE (with INNER, without
-// EARLY): level 0 arrives through asynchronous global->LDS copies one plane
-// ahead (see the staged loop below); the caller then also keeps columns
-// i0-2 .. i0+65 inside the grid and the plane below 2^32 bytes.
+// for kernels that inline several marches).  STAGE (without EARLY): level 0
+// arrives through asynchronous global->LDS copies one plane ahead (see the
+// staged loop below); the caller keeps the plane below 2^32 bytes, nx >= 2,
+// and -- when nx is odd -- the staged columns (68 from an even x at most 3
+// left of i0) inside the grid on the right; with INNER also on the left.
 template <int T, int R, bool NT, bool EARLY = false, bool SROW = true, bool INNER = false,
           bool STAGE = false>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
-                                          int lane_lo, int lane_hi) {
+                                          int lane_lo, int lane_hi, char* stage_lds = nullptr) {
     using S = TbShape<T, R>;
     const int lane = (int)(threadIdx.x & 63);
     const int i = i0 + lane;
@@ -170,7 +178,7 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
     // INNER loads read a clamped plane; a plane outside the grid is zeroed
     // after its loads are issued (wave-uniform)
     auto zero_out = [&](int k, double* a, int n) {
-        if constexpr (INNER) {
+        if constexpr (INNER || STAGE) {
             if (k < 0 || k >= nz) {
                 for (int q = 0; q < n; ++q) a[q] = 0.0;
             }
@@ -231,11 +239,16 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         store_hold();
         return;
     }
-    if constexpr (INNER && STAGE && !EARLY) {
-        // Staged level 0: every plane's level-0 rows (x = i0-2 .. i0+65, so
-        // the strip edges too) are copied global->LDS by 16-byte pieces into
-        // one of two per-wave buffers, one plane ahead, so the copies hold no
-        // registers and are in flight while a whole plane computes.  The
+    if constexpr (STAGE && !EARLY) {
+        // Staged level 0: every plane's level-0 rows (68 columns from the
+        // even x0 = i0-2 or i0-3, so the strip edges too) are copied
+        // global->LDS by 16-byte pieces into one of two per-wave buffers, one
+        // plane ahead, so the copies hold no registers and are in flight
+        // while a whole plane computes.  Pieces and rows outside the grid
+        // (boundary waves) are copied from clamped coordinates -- with x0
+        // even a piece never straddles x = 0, nor x = nx-1 when nx is even
+        // -- and the values read back are zeroed where the point lies
+        // outside; planes outside the grid are zeroed whole.  The
         // copies are inline assembly with their waits written out: at the
         // top of each iteration vmcnt(0) covers the copy of plane k+1 issued
         // in the previous iteration and the stores issued just before it
@@ -247,17 +260,20 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         constexpr int kPieces = S::nl(0) * 34;       // 16-byte pieces per plane
         constexpr int kCopies = (kPieces + 63) / 64;  // copy instructions per plane
         constexpr int kBuf = kCopies * 1024;         // bytes per plane buffer
-        __shared__ __attribute__((aligned(16))) char stg[4 * 2 * kBuf];
+        // stage_lds: the caller's LDS block of 4 waves x 2 buffers x kBuf bytes
         const int wv = wave_index();
-        char* mine = stg + wv * 2 * kBuf;
+        char* mine = stage_lds + wv * 2 * kBuf;
         const unsigned lds0 =
             (unsigned)(uintptr_t)((__attribute__((address_space(3))) char*)mine);
+        const int x0 = i0 - 2 - (i0 & 1);  // even
         unsigned poff[kCopies];  // lane's byte offset within a plane, per copy
 #pragma unroll
         for (int p = 0; p < kCopies; ++p) {
             const int g = p * 64 + lane;
             const int r = min(g / 34, S::nl(0) - 1), c = min(g - r * 34, 33);
-            poff[p] = (unsigned)(((size_t)(j0 - T + r) * nx + (size_t)(i0 - 2 + 2 * c)) * 8u);
+            const int jr = min(max(j0 - T + r, 0), ny - 1);
+            const int xr = min(max(x0 + 2 * c, 0), nx - 2);
+            poff[p] = (unsigned)(((size_t)jr * nx + (size_t)xr) * 8u);
         }
         auto stage = [&](int kp) {  // plane kp (clamped into the grid) -> buffer kp & 1
             const char* pb = (const char*)(src + (size_t)min(max(kp, 0), nz - 1) * plane);
@@ -272,8 +288,9 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         };
         // lane's x offset in a staged row: its own point, or (strip edges)
         // x = i0-1 on lane 0 and x = i0+64 on lane 63
-        const int xo = (lane + 2) * 8;
-        const int eo = lane == 0 ? 8 : lane == 63 ? 66 * 8 : xo;
+        const int sh = i0 - x0;  // 2 or 3
+        const int xo = (lane + sh) * 8;
+        const int eo = lane == 0 ? (sh - 1) * 8 : lane == 63 ? (64 + sh) * 8 : xo;
         auto rd = [&](int kp, int q, int off) -> double {
             return *(const double*)(mine + (kp & 1) * kBuf + q * kRowB + off);
         };
@@ -284,7 +301,7 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
             if (hold_p >= k0 && hold_p < k1) {
 #pragma unroll
                 for (int q = 0; q < R; ++q)
-                    if (lane_out)
+                    if (lane_out && (INNER || j0 + q < ny))
                         put<NT>(dst + (size_t)hold_p * plane + (size_t)(j0 + q) * nx + i, hold[q]);
             }
         };
@@ -294,9 +311,25 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             double ex[S::nl(1)];
 #pragma unroll
-            for (int q = 0; q < S::nl(0); ++q) fresh[q] = rd(k + 1, q, xo);
+            for (int q = 0; q < S::nl(0); ++q) {
+                const double v = rd(k + 1, q, xo);
+                if constexpr (INNER) {
+                    fresh[q] = v;
+                } else {
+                    const int j = j0 - T + q;
+                    fresh[q] = (xin && j >= 0 && j < ny) ? v : 0.0;
+                }
+            }
 #pragma unroll
-            for (int q = 0; q < S::nl(1); ++q) ex[q] = rd(k, q + 1, eo);
+            for (int q = 0; q < S::nl(1); ++q) {
+                const double v = rd(k, q + 1, eo);
+                if constexpr (INNER) {
+                    ex[q] = v;
+                } else {
+                    const int j = j0 - (T - 1) + q;
+                    ex[q] = (eok && j >= 0 && j < ny) ? v : 0.0;
+                }
+            }
             zero_out(k + 1, fresh, S::nl(0));
             zero_out(k, ex, S::nl(1));
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");

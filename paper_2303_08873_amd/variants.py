@@ -19,8 +19,8 @@ def jacobi_variants_blocks():
 
 # ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_DIRECT, 32, 4, 1, 0), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
-                    (FAM_JACOBI_ZREG_T3, 64, 4, 16, 0),
-                    (FAM_JACOBI_ZREG_T4, 64, 5, 32, AO_VF_NT_STORE | AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T3, 64, 4, 16, AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T4, 64, 4, 64, AO_VF_NT_STORE | AO_VF_STAGED),
                     (FAM_JACOBI_ZREG_T2, 64, 4, 4, AO_VF_HALO_PREFETCH)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
 STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
