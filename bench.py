@@ -488,7 +488,7 @@ def cosched_workload(steps: int, warmup: int):
     stream = torch.cuda.current_stream(dev)
     V = 11
     vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_COSCHED, f, 0, 0, 0) for f in range(V)]
-    judge = ao.region_declare_variants("bench_cosched_table", ao.AO_JACOBI7_F64, vs,
+    exh = ao.region_declare_variants("bench_cosched_table", ao.AO_JACOBI7_F64, vs,
                                        min_train_data=10 ** 9, model_type="exhaustive")
     nmax = 512 ** 3
     u0_d = synth.u01_torch(4242, nmax, dev)
@@ -504,14 +504,14 @@ def cosched_workload(steps: int, warmup: int):
     for q, (n, S, res) in enumerate(cases):
         a = (ao.jacobi_args(u0_d, out_d, n, n, n, S, 1) if res else
              ao.jacobi_args(u0_h, out_h, n, n, n, S, 0))
-        med = ao.region_profile(judge, a, warmup=1, reps=3, stream=stream, num_variants=V)
+        med = ao.region_profile(exh, a, warmup=1, reps=3, stream=stream, num_variants=V)
         table.append(med)
-        feats.append(ao.region_features(judge, a))
+        feats.append(ao.region_features(exh, a))
         _log(f"cosched n={n} S={S} resident={res}: best fraction "
              f"{int(np.argmin(med)) / 10:.1f} " + " ".join(f"{t * 1e3:.2f}" for t in med) + " ms")
     table = np.array(table)
     table_s = time.perf_counter() - t0
-    ao.region_destroy(judge)
+    ao.region_destroy(exh)
     region = ao.region_declare_variants("bench_cosched", ao.AO_JACOBI7_F64, vs,
                                         min_train_data=10 ** 9, model_type="mlp")
     # held out: whole grid sizes (192, 320, 448), every sweep count and residency

@@ -234,7 +234,7 @@ int region_features(ao_region* r, const ao_args* a, void* stream, float* feature
 #define AO_PROFILE_RECORD 1 /* append the timed runs to the profile database */
 
 /* Time variants in isolation (Table 1 begin/end timing) -- the exhaustive
- * selector and the judge of the learned one.  For each variant (all if
+ * selector and the yardstick of the learned one.  For each variant (all if
  * variant == -1): `warmup` untimed runs, then `reps` timed runs; writes the
  * median seconds to median_seconds[v] (num_variants entries when variant ==
  * -1, else 1 entry; a variant that cannot run gets +inf).  Synchronises.

@@ -119,19 +119,19 @@ def run(n_inputs=1000, n_online=100, iters=100, seed=40, max_dim=512, epochs=200
             return ao.jacobi_args(u0_d, out_d, nx, ny, nz, int(sw[q]), 1)
         return ao.jacobi_args(u0_h, out_h, nx, ny, nz, int(sw[q]), 0)
 
-    # the exhaustive table (the judge of every comparator)
-    judge = ao.region_declare_variants(f"protocol_table_{seed}", ao.AO_JACOBI7_F64, variants,
+    # the exhaustive table (the yardstick of every comparator)
+    exh = ao.region_declare_variants(f"protocol_table_{seed}", ao.AO_JACOBI7_F64, variants,
                                        min_train_data=10 ** 9, model_type="exhaustive")
     table = np.zeros((n_inputs, V))
     feats = []
     t0 = time.perf_counter()
     for q in range(n_inputs):
         a = args_for(q)
-        table[q] = ao.region_profile(judge, a, warmup=1, reps=5, stream=st, num_variants=V)
-        feats.append(list(ao.region_features(judge, a)))
+        table[q] = ao.region_profile(exh, a, warmup=1, reps=5, stream=st, num_variants=V)
+        feats.append(list(ao.region_features(exh, a)))
         if (q + 1) % 200 == 0:
             _log(f"exhaustive table: {q + 1} inputs ({time.perf_counter() - t0:.0f} s)")
-    ao.region_destroy(judge)
+    ao.region_destroy(exh)
     t_best = table.min(axis=1)
     t_static = table[:, STATIC_DEFAULT]
     every = np.arange(n_inputs)

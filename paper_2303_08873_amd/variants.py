@@ -3,8 +3,8 @@ as categorical variants are numbered from 0 in the order given, Sec. 3.1
 model_output clause)."""
 from __future__ import annotations
 
-from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_STAGED,
-                   FAM_JACOBI_DIRECT, FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
+from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_NT_STORE, AO_VF_STAGED,
+                   FAM_JACOBI_DIRECT, FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T3,
                    FAM_JACOBI_ZREG_T4, FAM_SPMV_BANDED,
                    FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, Variant)
 
@@ -19,17 +19,17 @@ def jacobi_variants_blocks():
 
 # ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_DIRECT, 32, 4, 1, 0), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
-                    (FAM_JACOBI_ZREG_T3, 64, 4, 16, AO_VF_STAGED),
-                    (FAM_JACOBI_ZREG_T4, 64, 4, 64, AO_VF_NT_STORE | AO_VF_STAGED),
-                    (FAM_JACOBI_ZREG_T2, 64, 4, 4, AO_VF_HALO_PREFETCH)]
+                    (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
 STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
 
 
 def jacobi_variants_sweep():
     """10 variants: 5 GPU block / tile shapes (one point per thread; the
-    register z-march with two, three or four sweeps per pass) and 5 host-CPU
-    cache-block shapes."""
+    register z-march with three or four sweeps per pass, level 0 staged,
+    with 4, 22 or 74 planes per block) and 5 host-CPU cache-block shapes."""
     out = [Variant(AO_TARGET_GPU, f, bx, by, bz, fl) for f, bx, by, bz, fl in JACOBI_SWEEP_GPU]
     out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]
     return out
