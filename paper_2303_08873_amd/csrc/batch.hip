@@ -257,10 +257,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
 // One pass of a three-sweep tile column: T = 1, 2 or 3 sweeps on lanes
 // 2 .. 61 of the strip starting at i0; two- and three-sweep passes of waves
 // whose columns and rows (with the T-row halo) lie inside the grid take the
-// march without per-lane selects.
+// march without per-lane selects.  Three-sweep passes receive level 0
+// through the staged global->LDS copies (stg: the block's staging area)
+// where the staged columns allow it: a plane below 2^32 bytes and, for odd
+// nx, the 68 staged columns (from the even x0 = i0-2 or i0-3) inside the
+// grid on the right -- and on both sides for the path without selects.
 template <int R>
 __device__ __forceinline__ void tri_column(int T, const double* src, double* dst, const Inst& in,
-                                           int i0, int j0, int z0, int k1) {
+                                           int i0, int j0, int z0, int k1, char* stg) {
     if (T == 1) {
         zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
     } else if (T == 2) {
@@ -273,7 +277,16 @@ __device__ __forceinline__ void tri_column(int T, const double* src, double* dst
                                                      2, 61);
     } else {
         const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 3 && j0 + R + 3 <= in.ny;
-        if (inner)
+        const int x0 = i0 - 2 - (i0 & 1);
+        const bool fits = in.nx >= 2 && (size_t)in.nx * (size_t)in.ny * 8u < ((size_t)1 << 32) &&
+                          (!(in.nx & 1) || x0 + 68 <= in.nx);
+        if (fits && inner && x0 >= 0 && x0 + 68 <= in.nx)
+            zm::tb_column<3, R, false, false, false, true, true>(src, dst, in.nx, in.ny, in.nz, i0,
+                                                                 j0, z0, k1, 2, 61, stg);
+        else if (fits)
+            zm::tb_column<3, R, false, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0,
+                                                                  j0, z0, k1, 2, 61, stg);
+        else if (inner)
             zm::tb_column<3, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
                                                            k1, 2, 61);
         else
@@ -292,6 +305,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused3(const Inst* __restric
     const int g = (int)gridDim.x;
     const int slot = xcd_slot((int)blockIdx.x, g);
     const int wave = (int)(threadIdx.x >> 6);
+    // staging area of the widest tile (4 rows per wave); a wave's staged
+    // march ends with its copies landed, so the next item reuses it at once
+    __shared__ __attribute__((aligned(16))) char stg[zm::stage_lds_bytes<3, 4>()];
     for (int w = slot; w < nitems; w += g) {
         const Item it = items[w];
         const Inst in = insts[it.inst];
@@ -308,11 +324,11 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused3(const Inst* __restric
         const int k1 = min(in.nz, it.z0 + c.tz);
         const int i0 = it.x0 - 2;
         if (R == 1)
-            tri_column<1>(T, src, dst, in, i0, j0, it.z0, k1);
+            tri_column<1>(T, src, dst, in, i0, j0, it.z0, k1, stg);
         else if (R == 2)
-            tri_column<2>(T, src, dst, in, i0, j0, it.z0, k1);
+            tri_column<2>(T, src, dst, in, i0, j0, it.z0, k1, stg);
         else
-            tri_column<4>(T, src, dst, in, i0, j0, it.z0, k1);
+            tri_column<4>(T, src, dst, in, i0, j0, it.z0, k1, stg);
     }
 }
 
