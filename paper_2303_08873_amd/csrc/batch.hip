@@ -257,8 +257,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
 // One pass of a three-sweep tile column: T = 1, 2 or 3 sweeps on lanes
 // 2 .. 61 of the strip starting at i0; two- and three-sweep passes of waves
 // whose columns and rows (with the T-row halo) lie inside the grid take the
-// march without per-lane selects.  Three-sweep passes receive level 0
-// through the staged global->LDS copies (stg: the block's staging area)
+// march without per-lane selects.  Two- and three-sweep passes receive
+// level 0 through the staged global->LDS copies (stg: the block's staging area)
 // where the staged columns allow it: a plane below 2^32 bytes and, for odd
 // nx, the 68 staged columns (from the even x0 = i0-2 or i0-3) inside the
 // grid on the right -- and on both sides for the path without selects.
@@ -269,7 +269,16 @@ __device__ __forceinline__ void tri_column(int T, const double* src, double* dst
         zm::tb_column<1, R, false, false, false>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0, k1, 2, 61);
     } else if (T == 2) {
         const bool inner = i0 >= 1 && i0 + 64 < in.nx && j0 >= 2 && j0 + R + 2 <= in.ny;
-        if (inner)
+        const int x0 = i0 - 2 - (i0 & 1);
+        const bool fits = in.nx >= 2 && (size_t)in.nx * (size_t)in.ny * 8u < ((size_t)1 << 32) &&
+                          (!(in.nx & 1) || x0 + 68 <= in.nx);
+        if (fits && inner && x0 >= 0 && x0 + 68 <= in.nx)
+            zm::tb_column<2, R, false, false, false, true, true>(src, dst, in.nx, in.ny, in.nz, i0,
+                                                                 j0, z0, k1, 2, 61, stg);
+        else if (fits)
+            zm::tb_column<2, R, false, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0,
+                                                                  j0, z0, k1, 2, 61, stg);
+        else if (inner)
             zm::tb_column<2, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
                                                            k1, 2, 61);
         else
