@@ -56,7 +56,8 @@ constexpr TileCfg kCands[] = {
     {kFused1, 62, 4, 16}, {kFused2, 62, 8, 16},  {kFused2, 62, 8, 32},  {kFused4, 62, 16, 16},
     {kFused4, 62, 16, 32}, {kFused1, 62, 4, 32},
     {kTri1, 60, 4, 16},    {kTri2, 60, 8, 16},   {kTri4, 60, 16, 16},   {kTri4, 60, 16, 32},
-    {kTri2, 60, 8, 32},
+    {kTri2, 60, 8, 32},    {kTri4, 60, 16, 24},  {kTri4, 60, 16, 12},   {kTri2, 60, 8, 24},
+    {kTri2, 60, 8, 8},
 };
 constexpr int kNumCands = (int)(sizeof(kCands) / sizeof(kCands[0]));
 // default candidate per bucket before autotuning
