@@ -18,7 +18,7 @@ def jacobi_variants_blocks():
 
 
 # ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
-JACOBI_SWEEP_GPU = [(FAM_JACOBI_DIRECT, 32, 4, 1, 0), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
+JACOBI_SWEEP_GPU = [(FAM_JACOBI_ZREG_T3, 64, 1, 1, AO_VF_STAGED), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
                     (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED),
                     (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED),
                     (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED)]
@@ -27,9 +27,11 @@ STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
 
 
 def jacobi_variants_sweep():
-    """10 variants: 5 GPU block / tile shapes (one point per thread; the
-    register z-march with three or four sweeps per pass, level 0 staged,
-    with 4, 22 or 74 planes per block) and 5 host-CPU cache-block shapes."""
+    """10 variants: 5 GPU block / tile shapes (one point per thread with
+    64x4 threads; the register z-march with three or four sweeps per pass,
+    level 0 staged: 1 row per wave and 1 plane per block for small grids,
+    4 rows per wave and 4, 22 or 74 planes per block) and 5 host-CPU
+    cache-block shapes."""
     out = [Variant(AO_TARGET_GPU, f, bx, by, bz, fl) for f, bx, by, bz, fl in JACOBI_SWEEP_GPU]
     out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]
     return out
