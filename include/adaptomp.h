@@ -294,7 +294,10 @@ int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen)
  * three-sweep tiles (the first pass then takes the S mod 3 remaining
  * sweeps), so an instance takes S, ceil(S/2) or ceil(S/3) passes.  The
  * three tile families run in three persistent kernels launched one after
- * the other in each pass.  use_graph != 0
+ * the other in each pass; the three-sweep kernel receives level 0 of its
+ * two- and three-sweep passes through global->LDS copies a plane ahead
+ * (48 KB of LDS per workgroup) wherever the staged columns fit the grid.
+ * use_graph != 0
  * launches all passes as one captured HIP graph (captured on first use,
  * re-captured after autotuning or batch_set_tiles).  Enqueued on
  * `stream`. */
