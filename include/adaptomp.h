@@ -82,7 +82,10 @@ enum ao_kind {
 enum ao_target { AO_TARGET_GPU = 0, AO_TARGET_HOST = 1 };
 
 enum ao_family {
-    AO_FAM_JACOBI_DIRECT = 0, /* GPU: one thread per point, block bx*by */
+    AO_FAM_JACOBI_DIRECT = 0, /* GPU: one thread per point, block bx*by (bx*by a multiple
+                                 of 64, at most 1024); a grid of at most 8192 points
+                                 runs all its sweeps in one launch of one workgroup
+                                 that holds the grid twice in LDS */
     AO_FAM_JACOBI_ZMARCH = 1, /* GPU: bx*by LDS plane tile + halo, marches bz planes */
     AO_FAM_JACOBI_HOST = 2,   /* host CPU (OpenMP): tiles bx (0 = whole row) by by rows */
     AO_FAM_JACOBI_ZREG = 3,   /* GPU: register z-march, strip bx (64|128) wide, by (1|2|4|8)

@@ -27,6 +27,12 @@ hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, doubl
 // Three or four sweeps at once (families ZREG_T3 / ZREG_T4): dst <- J^T(src).
 hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double* dst, int nx,
                                  int ny, int nz, hipStream_t s);
+// All `sweeps` sweeps dst <- J^sweeps(src) of a grid of at most 8192 points
+// in one launch of one workgroup (the grid held twice in LDS);
+// hipErrorInvalidConfiguration for a larger grid.
+bool lds_sweeps_fit(int nx, int ny, int nz);
+hipError_t jacobi_gpu_lds_sweeps(const double* src, double* dst, int nx, int ny, int nz,
+                                 int sweeps, hipStream_t s);
 hipError_t hbm_copy(const double* src, double* dst, int64_t n, bool nt, hipStream_t s);
 
 // Host (OpenMP) variant: S sweeps from u0 into out using tmp (N doubles) as

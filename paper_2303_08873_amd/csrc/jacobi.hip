@@ -86,6 +86,64 @@ __global__ __launch_bounds__(1024) void jac_direct(const double* __restrict__ sr
     store<NT>(dst + idx, v * kC);
 }
 
+// All S sweeps of a grid of at most kLdsPoints points in one workgroup: the
+// grid and its next sweep live in LDS (two copies), one barrier per sweep.
+// Each thread owns the points tid + 1024 m and keeps their neighbour masks
+// (bit 0..5: x-1, x+1, y-1, y+1, z-1, z+1 inside the grid) across sweeps.
+// Same sum order and ghost values as jac_direct.
+constexpr int kLdsPoints = 8192;
+constexpr int kLdsPer = kLdsPoints / 1024;
+__global__ __launch_bounds__(1024) void jac_lds_sweeps(const double* __restrict__ src,
+                                                       double* __restrict__ dst, int nx, int ny,
+                                                       int nz, int sweeps) {
+    __shared__ double g[2][kLdsPoints];
+    const int n = nx * ny * nz, plane = nx * ny, tid = (int)threadIdx.x;
+    int mask[kLdsPer];
+#pragma unroll
+    for (int m = 0; m < kLdsPer; ++m) {
+        const int p = tid + 1024 * m;
+        mask[m] = 0;
+        if (p < n) {
+            const int i = p % nx, t = p / nx, j = t % ny, k = t / ny;
+            mask[m] = (i > 0) | (i + 1 < nx) << 1 | (j > 0) << 2 | (j + 1 < ny) << 3 |
+                      (k > 0) << 4 | (k + 1 < nz) << 5;
+            g[0][p] = src[p];
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int s = 0; s < sweeps; ++s) {
+        const double* a = g[cur];
+        double* b = g[cur ^ 1];
+#pragma unroll
+        for (int m = 0; m < kLdsPer; ++m) {
+            const int p = tid + 1024 * m;
+            if (p < n) {
+                const int f = mask[m];
+                const double xm = (f & 1) ? a[p - 1] : 0.0;
+                const double xp = (f & 2) ? a[p + 1] : 0.0;
+                const double ym = (f & 4) ? a[p - nx] : 0.0;
+                const double yp = (f & 8) ? a[p + nx] : 0.0;
+                const double zm = (f & 16) ? a[p - plane] : 0.0;
+                const double zp = (f & 32) ? a[p + plane] : 0.0;
+                double v = xm + xp;
+                v = v + ym;
+                v = v + yp;
+                v = v + zm;
+                v = v + zp;
+                b[p] = v * kC;
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int m = 0; m < kLdsPer; ++m) {
+        const int p = tid + 1024 * m;
+        if (p < n) dst[p] = g[cur][p];
+    }
+}
+
 template <bool NT>
 __global__ __launch_bounds__(1024) void jac_zmarch(const double* __restrict__ src,
                                                    double* __restrict__ dst, int nx, int ny,
@@ -554,6 +612,17 @@ __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src,
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace
+
+bool lds_sweeps_fit(int nx, int ny, int nz) {
+    return nx > 0 && ny > 0 && nz > 0 && (int64_t)nx * ny * nz <= kLdsPoints;
+}
+
+hipError_t jacobi_gpu_lds_sweeps(const double* src, double* dst, int nx, int ny, int nz,
+                                 int sweeps, hipStream_t s) {
+    if (!lds_sweeps_fit(nx, ny, nz) || sweeps < 0) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(jac_lds_sweeps, dim3(1), dim3(1024), 0, s, src, dst, nx, ny, nz, sweeps);
+    return hipGetLastError();
+}
 
 hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst, int nx, int ny,
                             int nz, hipStream_t s) {

@@ -548,11 +548,19 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
                 return P == 2 ? jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s)
                               : jacobi_gpu_multi_sweep(v, src, dst, nx, ny, nz, s);
             };
+            // the one-point-per-thread family runs a grid of at most 8192
+            // points in one workgroup's LDS, all S sweeps in one launch
+            // (only for a block shape its sweep kernel accepts)
+            const bool lds_all = v.family == AO_FAM_JACOBI_DIRECT && S >= 1 &&
+                                 lds_sweeps_fit(nx, ny, nz) && v.bx > 0 && v.by > 0 &&
+                                 (int64_t)v.bx * v.by <= 1024 && (v.bx * v.by) % 64 == 0;
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess && n > 0) {
                 if (a->resident) {
                     if (S == 0) {
                         e = hipMemcpyAsync(a->out, a->u0, n * 8, hipMemcpyDeviceToDevice, s);
+                    } else if (lds_all) {
+                        e = jacobi_gpu_lds_sweeps(a->u0, a->out, nx, ny, nz, S, s);
                     } else {
                         const double* src = a->u0;
                         for (int k = 0; k < L && e == hipSuccess; ++k) {
@@ -565,9 +573,14 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
                     e = hipMemcpyAsync(r->d_a, a->u0, n * 8, hipMemcpyHostToDevice, s);
                     double* p = r->d_a;
                     double* q = r->d_b;
-                    for (int k = 0; k < L && e == hipSuccess; ++k) {
-                        e = launch(k, p, q);
+                    if (lds_all) {
+                        if (e == hipSuccess) e = jacobi_gpu_lds_sweeps(p, q, nx, ny, nz, S, s);
                         std::swap(p, q);
+                    } else {
+                        for (int k = 0; k < L && e == hipSuccess; ++k) {
+                            e = launch(k, p, q);
+                            std::swap(p, q);
+                        }
                     }
                     if (e == hipSuccess)
                         e = hipMemcpyAsync(a->out, p, n * 8, hipMemcpyDeviceToHost, s);

@@ -350,3 +350,35 @@ def test_full_size_512_sampled_windows(env, orc):
             assert np.array_equal(got, np.array(want))
         else:
             assert torch.equal(out, ref), f"variant {v} differs from variant 0 at full size"
+
+
+@pytest.mark.parametrize("shape,S", [((16, 16, 32), 7), ((8193, 1, 1), 2), ((1, 8192, 1), 3),
+                                     ((20, 20, 20), 1), ((3, 5, 7), 20), ((16, 16, 33), 2)])
+def test_direct_family_small_grids_in_lds(env, orc, shape, S):
+    # grids of at most 8192 points run all sweeps in one workgroup's LDS
+    # (16x16x32, 1x8192x1, 20^3, 3x5x7); 8193x1x1 and 16x16x33 just past the
+    # limit take the per-sweep launches; both residencies, bit-identical to
+    # the oracle
+    ao, torch, dev, st = env
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=91 + nz + S)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, bx, by, 1, 0)
+          for bx, by in ((64, 4), (32, 8), (64, 16))]
+    h = ao.region_declare_variants(f"gpu_lds_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                   model_type="roundrobin")
+    for resident in (1, 0):
+        if resident:
+            a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+        else:
+            uh = torch.from_numpy(u0_h).pin_memory()
+            oh = torch.empty(uh.shape, dtype=torch.float64).pin_memory()
+            a = ao.jacobi_args(uh, oh, nx, ny, nz, S, resident=0)
+        for v in range(len(vs)):
+            (out if resident else oh).fill_(-1.0)
+            ao.region_run(h, a, stream=st, variant=v)
+            torch.cuda.synchronize()
+            _check((out if resident else oh).cpu().numpy(), want)
+    ao.region_destroy(h)
