@@ -159,10 +159,16 @@ def spmv_bytes(n: int, nnz: int) -> int:
 
 def stencil_features(nx: int, ny: int, nz: int, sweeps: int, resident: int) -> np.ndarray:
     """[log2 nx, log2 ny, log2 nz, S, log2(bytes), device flag], FP32 as the
-    Apollo feature values are floats (Table 1).  bytes = 16*N*S."""
+    Apollo feature values are floats (Table 1).  bytes = 16*N*S.  Reading
+    for empty regions (the paper's feature values are never zero): an
+    extent of 0 and a byte count of 0 enter as 0, the value of an extent of
+    one."""
     b = jacobi_bytes(nx, ny, nz, sweeps)
-    f = [math.log2(nx), math.log2(ny), math.log2(nz), float(sweeps),
-         math.log2(b) if b > 0 else 0.0, float(resident)]
+
+    def lg(v):
+        return math.log2(v) if v > 0 else 0.0
+
+    f = [lg(nx), lg(ny), lg(nz), float(sweeps), lg(b), float(resident)]
     return np.asarray(f, dtype=np.float64).astype(np.float32)
 
 

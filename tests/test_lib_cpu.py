@@ -288,3 +288,27 @@ def test_banded_spmv_variant_validation(ao):
         with pytest.raises(ao.AdaptError):
             ao.region_declare_variants(f"banded_bad_{b}_{nb}", ao.AO_CSR_SPMV_F64,
                                        [ao.Variant(G, ao.FAM_SPMV_BANDED, b, nb, 1, 0)])
+
+
+@pytest.mark.parametrize("resident", [0, 1])
+def test_stencil_features_match_oracle(ao, orc, resident):
+    # The feature vector the runtime feeds the cost model for a Jacobi region
+    # (Sec. 3.1 features clause) equals the oracle's, for ragged, degenerate
+    # (extent 0 or 1) and large shapes and sweep counts.  Host arithmetic:
+    # no GPU is needed and the buffer addresses are never dereferenced.
+    h = ao.region_declare_variants(f"feat_stencil_{resident}", ao.AO_JACOBI7_F64,
+                                   ao.jacobi_variants_blocks(), model_type="roundrobin")
+    shapes = [(64, 32, 16, 10), (1, 1, 1, 1), (0, 5, 7, 3), (5, 0, 7, 20), (7, 5, 0, 5),
+              (37, 29, 13, 3), (512, 512, 512, 20), (8, 512, 100, 5), (3, 1, 1000, 0),
+              (1 << 20, 1, 1, 2), (160, 160, 160, 7), (2, 3, 1, 1)]
+    for nx, ny, nz, S in shapes:
+        a = ao.Args()
+        a.kind, a.resident = ao.AO_JACOBI7_F64, resident
+        a.nx, a.ny, a.nz, a.sweeps = nx, ny, nz, S
+        n = nx * ny * nz
+        if n > 0:
+            a.u0, a.out = 1 << 20, (1 << 20) + 8 * n + 64
+        got = np.asarray(ao.region_features(h, a), dtype=np.float32)
+        want = orc.stencil_features(nx, ny, nz, S, resident)
+        assert got.tobytes() == want.tobytes(), ((nx, ny, nz, S), got, want)
+    ao.region_destroy(h)

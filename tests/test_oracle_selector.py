@@ -161,3 +161,75 @@ def test_dataset_merges_duplicates_by_median(orc):
     ds = orc.build_dataset(recs, 2)
     assert list(ds["seconds"]) == [2.0, 4.0] and list(ds["variant"]) == [0, 1]
     assert ds["y"].sum() == pytest.approx(0.0)
+
+
+def test_adam_constant_gradient_every_step(orc):
+    # Under a constant gradient g the moments are geometric sums:
+    # m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the bias-corrected
+    # m_hat = g and v_hat = g^2 at every t and each step moves theta by
+    # lr * g / (|g| + eps).  A bias correction with b*t in place of b^t, or a
+    # moment recursion with the weights swapped, already differs at t = 2.
+    theta0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -4.0, 1e-3, 2.5])
+    step = 1e-3 * g / (np.abs(g) + 1e-8)
+    theta, m, v = theta0.copy(), np.zeros(4), np.zeros(4)
+    for t in range(1, 41):
+        theta, m, v = orc.adam_step(theta, g, m, v, t)
+        assert np.allclose(m, (1.0 - 0.9 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1.0 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(theta, theta0 - t * step, rtol=0, atol=1e-13 * t)
+
+
+def test_adam_step_is_invariant_to_gradient_scale(orc):
+    # m_hat scales with c and sqrt(v_hat) with |c|, so for c > 0 the update
+    # is the same up to eps: a v built from g rather than g^2 breaks this.
+    import synth
+    theta0 = synth.u01(31, 8) - 0.5
+    gs = [synth.u01(32 + k, 8) - 0.5 for k in range(5)]
+    runs = []
+    for c in (1.0, 64.0):
+        th, m, v = theta0.copy(), np.zeros(8), np.zeros(8)
+        for t, g in enumerate(gs, start=1):
+            th, m, v = orc.adam_step(th, c * g, m, v, t)
+        runs.append(th)
+    assert np.allclose(runs[0], runs[1], rtol=0, atol=1e-9)
+    assert not np.allclose(runs[0], theta0, rtol=0, atol=1e-4)
+
+
+def test_dataset_zscore_and_std_floor(orc):
+    # Three records on two features: feature 0 = 1, 2, 3 (mean 2, population
+    # std sqrt(2/3)); feature 1 constant 10 (std 0, floored at 1e-6, so it
+    # normalises to 0); the unused feature slots 2..5 are 0 and stay 0.
+    recs = [([1.0, 10.0], 0, math.exp(1.0)), ([2.0, 10.0], 1, math.exp(2.0)),
+            ([3.0, 10.0], 0, math.exp(3.0))]
+    ds = orc.build_dataset(recs, 2)
+    s = math.sqrt(2.0 / 3.0)
+    assert np.allclose(ds["X"][:, 0], [-1.0 / s, 0.0, 1.0 / s], rtol=1e-15, atol=0)
+    assert np.all(ds["X"][:, 1:] == 0.0)
+    assert list(ds["mu"][:2]) == [2.0, 10.0] and ds["sd"][0] == pytest.approx(s, rel=1e-15)
+    assert np.all(ds["sd"][1:] == 1e-6)
+    assert np.allclose(ds["y"], [-1.0, 0.0, 1.0], rtol=0, atol=1e-15)
+    assert ds["y_mean"] == pytest.approx(2.0, rel=1e-15)
+    assert ds["mask"].tolist() == [[1.0 if v == w else 0.0 for v in range(12)] for w in (0, 1, 0)]
+    # a spread below the floor: 0, 2^-24, 2^-23 have population std
+    # 2^-24 * sqrt(2/3) < 1e-6, so they divide by the floor
+    tiny = [([0.0], 0, 1.0), ([2.0 ** -24], 0, 1.0), ([2.0 ** -23], 0, 1.0)]
+    X = orc.build_dataset(tiny, 1)["X"][:, 0]
+    assert np.allclose(X, [-2.0 ** -24 / 1e-6, 0.0, 2.0 ** -24 / 1e-6], rtol=1e-14, atol=0)
+
+
+def test_mlp_init_he_uniform(orc):
+    # He-uniform: W ~ U(-sqrt(6/fan_in), +sqrt(6/fan_in)) with fan_in the
+    # layer's input width (6, 64, 64), variance 2/fan_in; biases zero.
+    p = orc.mlp_unflatten(orc.mlp_init(11))
+    for w, fan_in in (("W1", 6), ("W2", 64), ("W3", 64)):
+        bound = math.sqrt(6.0 / fan_in)
+        a = p[w].reshape(-1)
+        assert np.all(np.abs(a) < bound)
+        assert np.max(np.abs(a)) > 0.9 * bound          # the draws fill the interval
+        assert abs(np.var(a) / (2.0 / fan_in) - 1.0) < 0.15
+        assert abs(np.mean(a)) < 0.15 * bound
+    for b in ("b1", "b2", "b3"):
+        assert np.all(p[b] == 0.0)
+    assert not np.array_equal(orc.mlp_init(11), orc.mlp_init(12))
+    assert np.array_equal(orc.mlp_init(11), orc.mlp_init(11))

@@ -142,3 +142,20 @@ def test_generator_structure():
         c = col[rp[i]:rp[i + 1]]
         assert np.all(np.diff(c) > 0) and c.min() >= 0 and c.max() < n
     assert np.all(x >= -1.0) and np.all(x < 1.0)
+
+
+def test_byte_counts_are_the_arrays_touched_once(orc):
+    # One SpMV reads row_ptr, col, val and x once and writes y once; one
+    # relaxation sweep also reads b and diag once; one Jacobi sweep reads
+    # and writes the grid once.  Counted from the arrays themselves.
+    import synth
+    for n, seed in ((1, 3), (257, 4), (4000, 5)):
+        m = synth.csr_matrix(n, seed=seed, mean=6.0, max_len=50)
+        y = np.empty(n)
+        arrays = (m["row_ptr"], m["col"], m["val"], m["x"], y)
+        assert orc.spmv_bytes(n, int(m["col"].size)) == sum(a.nbytes for a in arrays)
+        b, d = np.empty(n), np.empty(n)
+        assert orc.relax_bytes(n, int(m["col"].size)) == sum(a.nbytes for a in arrays + (b, d))
+    for shape, S in (((3, 4, 5), 1), ((17, 1, 9), 7), ((0, 4, 4), 3)):
+        u = synth.grid_u01(*shape, seed=1)
+        assert orc.jacobi_bytes(*shape, S) == S * 2 * u.nbytes
