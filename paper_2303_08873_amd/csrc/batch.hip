@@ -263,6 +263,20 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused(const Inst* __restrict
 // where the staged columns allow it: a plane below 2^32 bytes and, for odd
 // nx, the 68 staged columns (from the even x0 = i0-2 or i0-3) inside the
 // grid on the right -- and on both sides for the path without selects.
+// Waves of one block run items of different (T, R) with no barrier between
+// them (a wave skips an item at once when its rows lie outside the grid), so
+// every staged march of the three-sweep kernel takes one fixed per-wave slot,
+// that of the widest tile: wave w owns bytes [w * kStageWave, (w+1) *
+// kStageWave) of the block's staging area whatever item it is on.
+constexpr int kStageWave = zm::stage_wave_bytes<3, 4>();
+template <int T, int R>
+constexpr bool slot_fits() {
+    return zm::stage_wave_bytes<T, R>() <= kStageWave && 4 * kStageWave == zm::stage_lds_bytes<3, 4>();
+}
+static_assert(slot_fits<2, 1>() && slot_fits<2, 2>() && slot_fits<2, 4>() && slot_fits<3, 1>() &&
+                  slot_fits<3, 2>() && slot_fits<3, 4>(),
+              "every staged (T, R) of the three-sweep tiles fits the fixed per-wave slot");
+
 template <int R>
 __device__ __forceinline__ void tri_column(int T, const double* src, double* dst, const Inst& in,
                                            int i0, int j0, int z0, int k1, char* stg) {
@@ -275,10 +289,10 @@ __device__ __forceinline__ void tri_column(int T, const double* src, double* dst
                           (!(in.nx & 1) || x0 + 68 <= in.nx);
         if (fits && inner && x0 >= 0 && x0 + 68 <= in.nx)
             zm::tb_column<2, R, false, false, false, true, true>(src, dst, in.nx, in.ny, in.nz, i0,
-                                                                 j0, z0, k1, 2, 61, stg);
+                                                                 j0, z0, k1, 2, 61, stg, kStageWave);
         else if (fits)
             zm::tb_column<2, R, false, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0,
-                                                                  j0, z0, k1, 2, 61, stg);
+                                                                  j0, z0, k1, 2, 61, stg, kStageWave);
         else if (inner)
             zm::tb_column<2, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
                                                            k1, 2, 61);
@@ -292,10 +306,10 @@ __device__ __forceinline__ void tri_column(int T, const double* src, double* dst
                           (!(in.nx & 1) || x0 + 68 <= in.nx);
         if (fits && inner && x0 >= 0 && x0 + 68 <= in.nx)
             zm::tb_column<3, R, false, false, false, true, true>(src, dst, in.nx, in.ny, in.nz, i0,
-                                                                 j0, z0, k1, 2, 61, stg);
+                                                                 j0, z0, k1, 2, 61, stg, kStageWave);
         else if (fits)
             zm::tb_column<3, R, false, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0,
-                                                                  j0, z0, k1, 2, 61, stg);
+                                                                  j0, z0, k1, 2, 61, stg, kStageWave);
         else if (inner)
             zm::tb_column<3, R, false, false, false, true>(src, dst, in.nx, in.ny, in.nz, i0, j0, z0,
                                                            k1, 2, 61);
@@ -315,9 +329,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_fused3(const Inst* __restric
     const int g = (int)gridDim.x;
     const int slot = xcd_slot((int)blockIdx.x, g);
     const int wave = (int)(threadIdx.x >> 6);
-    // staging area of the widest tile (4 rows per wave); a wave's staged
-    // march ends with its copies landed, so the next item reuses it at once
-    __shared__ __attribute__((aligned(16))) char stg[zm::stage_lds_bytes<3, 4>()];
+    // staging area of the widest tile (4 rows per wave), one fixed slot per
+    // wave; a wave's staged march ends with its copies landed and its reads
+    // done, so its next item reuses the slot at once
+    __shared__ __attribute__((aligned(16))) char stg[4 * kStageWave];
     for (int w = slot; w < nitems; w += g) {
         const Item it = items[w];
         const Inst in = insts[it.inst];

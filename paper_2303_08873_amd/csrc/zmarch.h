@@ -36,10 +36,13 @@ __device__ __forceinline__ void put(double* p, double v) {
 
 template <int T, int R>
 struct TbShape;
-// LDS bytes a block of 4 waves needs for the staged level 0 (two plane
-// buffers of 16-byte pieces per wave, 34 pieces per staged row)
+// LDS bytes one wave needs for the staged level 0 (two plane buffers of
+// 16-byte pieces, 34 pieces per staged row, one 1 KiB copy per 64 pieces),
+// and a block of 4 waves
 template <int T, int R>
-constexpr int stage_lds_bytes() { return 4 * 2 * (((R + 2 * T) * 34 + 63) / 64) * 1024; }
+constexpr int stage_wave_bytes() { return 2 * (((R + 2 * T) * 34 + 63) / 64) * 1024; }
+template <int T, int R>
+constexpr int stage_lds_bytes() { return 4 * stage_wave_bytes<T, R>(); }
 
 template <int T, int R>
 struct TbShape {
@@ -137,12 +140,15 @@ __device__ __forceinline__ void tb_rotate(double* below, double* centre, const d
 // arrives through asynchronous global->LDS copies one plane ahead (see the
 // staged loop below); the caller keeps the plane below 2^32 bytes, nx >= 2,
 // and -- when nx is odd -- the staged columns (68 from an even x at most 3
-// left of i0) inside the grid on the right; with INNER also on the left.
+// left of i0) inside the grid on the right; with INNER also on the left;
+// wave w stages in bytes [w * wave_bytes, w * wave_bytes +
+// stage_wave_bytes<T, R>()) of stage_lds.
 template <int T, int R, bool NT, bool EARLY = false, bool SROW = true, bool INNER = false,
           bool STAGE = false>
 __device__ __forceinline__ void tb_column(const double* __restrict__ src, double* __restrict__ dst,
                                           int nx, int ny, int nz, int i0, int j0, int k0, int k1,
-                                          int lane_lo, int lane_hi, char* stage_lds = nullptr) {
+                                          int lane_lo, int lane_hi, char* stage_lds = nullptr,
+                                          int wave_bytes = stage_wave_bytes<T, R>()) {
     using S = TbShape<T, R>;
     const int lane = (int)(threadIdx.x & 63);
     const int i = i0 + lane;
@@ -260,9 +266,13 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         constexpr int kPieces = S::nl(0) * 34;       // 16-byte pieces per plane
         constexpr int kCopies = (kPieces + 63) / 64;  // copy instructions per plane
         constexpr int kBuf = kCopies * 1024;         // bytes per plane buffer
-        // stage_lds: the caller's LDS block of 4 waves x 2 buffers x kBuf bytes
+        // stage_lds: the caller's LDS block, one slot of wave_bytes (at least
+        // 2 buffers x kBuf bytes) per wave.  A caller whose waves run items of
+        // different (T, R) without a barrier between them passes one fixed
+        // stride for all, so a wave's slot never moves into a neighbour's.
+        static_assert(2 * kBuf == stage_wave_bytes<T, R>(), "staging slot size");
         const int wv = wave_index();
-        char* mine = stage_lds + wv * 2 * kBuf;
+        char* mine = stage_lds + wv * wave_bytes;
         const unsigned lds0 =
             (unsigned)(uintptr_t)((__attribute__((address_space(3))) char*)mine);
         const int x0 = i0 - 2 - (i0 & 1);  // even

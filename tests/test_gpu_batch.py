@@ -45,7 +45,7 @@ def _reference(ao, torch, st, ins, bufs):
 
 def _check(torch, bufs, refs, tag):
     for q, ((u0, out), r) in enumerate(zip(bufs, refs)):
-        assert torch.equal(out, r), f"{tag}: instance {q} differs from its standalone run"
+        assert torch.equal(out, r), f"{tag}: instance {q} differs from its reference"
 
 
 def test_batch_small_mixed_against_oracle(env, orc):
@@ -63,12 +63,22 @@ def test_batch_small_mixed_against_oracle(env, orc):
     ao.batch_destroy(b)
 
 
-def test_batch_256_uneven_graph_and_autotune(env):
-    # 256 grids, each dimension log-uniform in [8, 256] (seed 3), 5 sweeps
+def _oracle_refs(torch, orc, bufs, shapes, sweeps):
+    refs = []
+    for (u0, _), (nx, ny, nz), s in zip(bufs, shapes, sweeps):
+        want = orc.jacobi7(u0.cpu().numpy(), int(nx), int(ny), int(nz), int(s))
+        refs.append(torch.from_numpy(want).to(u0.device))
+    return refs
+
+
+def test_batch_256_uneven_graph_and_autotune(env, orc):
+    # 256 grids, each dimension log-uniform in [8, 256] (seed 3), 5 sweeps:
+    # every grid compared with the serial oracle, eager, after autotuning and
+    # on every graph replay
     ao, torch, dev, st = env
     shapes = synth.batch_shapes(256, 8, 256, seed=3)
     ins, bufs = _instances(ao, torch, dev, shapes, [5] * 256, 3000)
-    refs = _reference(ao, torch, st, ins, bufs)
+    refs = _oracle_refs(torch, orc, bufs, shapes, [5] * 256)
     b = ao.batch_create(ins)
     inst, items, tiles = ao.batch_info(b)
     assert sum(inst) == 256 and all(i > 0 for i, c in zip(items, inst) if c > 0)
@@ -116,4 +126,35 @@ def test_every_tile_candidate_bit_identical(env, orc):
             ao.batch_run(b, stream=st, use_graph=use_graph)
             torch.cuda.synchronize()
             _check(torch, bufs, refs, f"candidate {c} {tile} graph={use_graph}")
+    ao.batch_destroy(b)
+
+
+def test_three_sweep_tiles_of_different_rows_across_buckets(env, orc):
+    # the waves of one block run items of different (T, R) back to back:
+    # three-sweep tiles with 1, 2 and 4 rows per wave on neighbouring buckets,
+    # sweep counts whose remainders mix one-, two- and three-sweep first
+    # passes, and grids whose upper waves have no rows (they skip the item at
+    # once); every instance compared with the oracle, eager and on graph
+    # replays
+    ao, torch, dev, st = env
+    shapes = [(12, 5, 9), (16, 13, 3), (30, 6, 17), (24, 31, 8), (60, 9, 33), (64, 3, 20),
+              (100, 7, 12), (128, 19, 5), (130, 11, 6), (200, 37, 4), (61, 2, 40), (121, 5, 9)]
+    sweeps = [5, 4, 6, 7, 5, 2, 4, 3, 5, 7, 1, 6]
+    ins, bufs = _instances(ao, torch, dev, shapes, sweeps, 2400)
+    refs = _oracle_refs(torch, orc, bufs, shapes, sweeps)
+    b = ao.batch_create(ins)
+    cands = ao.batch_candidates()
+    tri = {r: [c for c, t in enumerate(cands) if t[0] == 20 + r] for r in (1, 2, 4)}
+    assert all(tri[r] for r in (1, 2, 4))
+    plans = [[tri[1][0], tri[2][0], tri[4][0], tri[2][-1], tri[1][-1]],
+             [tri[4][0], tri[1][0], tri[2][0], tri[1][-1], tri[4][-1]],
+             [tri[2][0], tri[4][-1], tri[1][-1], tri[4][0], tri[2][-1]]]
+    for plan in plans:
+        ao.batch_set_tiles(b, plan)
+        for use_graph in (False, True, True):
+            for _, out in bufs:
+                out.fill_(float("nan"))
+            ao.batch_run(b, stream=st, use_graph=use_graph)
+            torch.cuda.synchronize()
+            _check(torch, bufs, refs, f"tiles {plan} graph={use_graph}")
     ao.batch_destroy(b)

@@ -2,7 +2,7 @@
 the C ABI: every variant bit-identical to every other and to the oracle
 (which sums in the same order; the bound is elementwise |g-o| <= 1e-12|o|,
 met here with zero error), on ragged shapes, both residencies, edge cases,
-and the full 512^3 x 20 workload on sampled windows."""
+and the full 512^3 x 20 workload on every point."""
 import math
 
 import numpy as np
@@ -316,40 +316,28 @@ def test_edge_cases(env, orc):
     assert math.isinf(med[0]) and math.isfinite(med[1])
 
 
-def test_full_size_512_sampled_windows(env, orc):
-    # 512^3, 20 sweeps, device-resident, every GPU variant of the size sweep.
-    # The value at p after S sweeps depends only on u0 within distance S, so
-    # the oracle on the window [p-S, p+S]^3 (clipped to the grid, zero ghost
-    # layer outside) gives it exactly.
+def test_full_size_512_every_variant_against_the_oracle(env, orc):
+    # 512^3, 20 sweeps, device-resident: the whole output grid of every GPU
+    # variant of the size sweep compared element by element with one run of
+    # the serial oracle (about 4 s of host time)
     ao, torch, dev, st = env
     n, S = 512, 20
     u0 = synth.grid_u01_torch(n, n, n, seed=2009, device=dev)
+    want = torch.from_numpy(orc.jacobi7(u0.cpu().numpy(), n, n, n, S)).to(dev)
     out = torch.empty_like(u0)
     h = ao.region_declare_variants("gpu_full", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep()[:5],
                                    model_type="roundrobin")
     a = ao.jacobi_args(u0, out, n, n, n, S)
-    pts = [(0, 0, 0), (511, 511, 511), (255, 17, 300), (3, 500, 44), (511, 0, 256), (100, 200, 511)]
-    u3 = u0.view(n, n, n)
-    ref = None
     for v in range(5):
         out.fill_(-1.0)
         ao.region_run(h, a, stream=st, variant=v)
         torch.cuda.synchronize()
-        o3 = out.view(n, n, n)
-        got = torch.stack([o3[k, j, i] for i, j, k in pts]).cpu().numpy()
-        if ref is None:
-            ref = out.clone()
-            want = []
-            for i, j, k in pts:
-                lo = [max(0, c - S) for c in (i, j, k)]
-                hi = [min(n, c + S + 1) for c in (i, j, k)]
-                win = u3[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous().cpu().numpy()
-                wz, wy, wx = win.shape
-                r = orc.jacobi7(win.reshape(-1), wx, wy, wz, S).reshape(wz, wy, wx)
-                want.append(r[k - lo[2], j - lo[1], i - lo[0]])
-            assert np.array_equal(got, np.array(want))
-        else:
-            assert torch.equal(out, ref), f"variant {v} differs from variant 0 at full size"
+        if not torch.equal(out, want):
+            bad = int((out != want).sum())
+            rel = float(((out - want).abs() / want.abs().clamp_min(1e-300)).max())
+            pytest.fail(f"variant {v}: {bad} of {n ** 3} points differ from the oracle "
+                        f"(max rel {rel:g})")
+    ao.region_destroy(h)
 
 
 @pytest.mark.parametrize("shape,S", [((16, 16, 32), 7), ((8193, 1, 1), 2), ((1, 8192, 1), 3),
