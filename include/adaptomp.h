@@ -312,6 +312,13 @@ int batch_run(ao_batch* b, void* stream, int use_graph);
  * per 64-lane strip). */
 int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz);
 
+/* The least HBM traffic one batch_run can move with the tiles in use: each
+ * pass reads every point of its instance once and writes it once, so
+ * 16 B x points x passes summed over the instances (the sweeps fused in a
+ * pass stay on chip).  Written to *bytes; the roofline of a batched run is
+ * taken against it. */
+int batch_min_traffic(const ao_batch* b, double* bytes);
+
 /* The candidate tile table the autotuner searches: returns its length and,
  * when tiles is not NULL, writes (kind, tx, ty, tz) per candidate into
  * tiles[4 * length]; kind 0 = one point per thread, 1|2|4 = register
@@ -388,6 +395,19 @@ const char* ao_last_error(void);
  * bandwidth is compared with, and the calibration kernel of the byte
  * counters.  nontemporal != 0 uses streaming stores. */
 int ao_hbm_copy(const double* src, double* dst, int64_t n, int nontemporal, void* stream);
+
+/* Random-gather probe: the memory access of a gather-per-nonzero SpMV
+ * (Sec. 4, the irregular AMGMk-style region) and nothing else.  idx[0..m)
+ * (int32, device) is streamed once, x[idx[k]] (FP64, device, nx entries;
+ * indices outside [0, nx) read x[0]) is gathered, and the gathered values
+ * of each wave (512 entries) are summed into one double of out: out holds
+ * 4 * ceil(m / 2048) doubles (device, caller-owned); workgroup g covers
+ * entries [2048 g, 2048 g + 2048) and lands on XCD g % 8 under round-robin
+ * dispatch.  Passing a matrix's column array as idx times the gathers of
+ * an SpMV of that matrix without its value stream.  Enqueued on stream;
+ * AO_EINVAL for bad arguments, nothing enqueued. */
+int ao_gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, double* out,
+                    void* stream);
 
 /* Number of compute units of the current device (0 if none). */
 int ao_device_cus(void);

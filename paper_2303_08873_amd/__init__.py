@@ -17,9 +17,9 @@ from ._lib import (  # noqa: F401
     FAM_JACOBI_HOST, FAM_JACOBI_ZMARCH, FAM_JACOBI_ZREG, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
     FAM_JACOBI_ZREG_T4, FAM_JACOBI_COSCHED,
     FAM_SPMV_BANDED, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, AdaptError, Args, Stats,
-    TrainOpts, Variant, lib, lib_path, ao_last_error, ao_device_cus, ao_hbm_copy, ao_mlp_adam, ao_mlp_forward,
+    TrainOpts, Variant, lib, lib_path, ao_last_error, ao_device_cus, ao_gather_probe, ao_hbm_copy, gather_probe_out_len, ao_mlp_adam, ao_mlp_forward,
     ao_mlp_grad, batch_autotune, batch_candidates, batch_create, batch_destroy, batch_info,
-    batch_run, batch_set_tiles,
+    batch_min_traffic, batch_run, batch_set_tiles,
     region_clear_memo, region_declare_variants, region_destroy, region_features, region_load, region_profile,
     region_record, region_records, region_run, region_save, region_stats, selector_select, selector_train,
     jacobi_args, relax_args, spmv_args)

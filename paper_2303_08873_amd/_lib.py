@@ -98,6 +98,7 @@ def _load():
         "batch_run": [P, P, I],
         "batch_info": [P, P, P, P],
         "batch_candidates": [P],
+        "batch_min_traffic": [P, P],
         "batch_set_tiles": [P, P],
         "batch_destroy": [P],
         "ao_mlp_forward": [P, P, I, P, P],
@@ -111,6 +112,7 @@ def _load():
         "region_destroy": [P],
         "ao_device_cus": [],
         "ao_hbm_copy": [P, P, ctypes.c_int64, I, P],
+        "ao_gather_probe": [P, P, ctypes.c_int64, ctypes.c_int64, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -256,6 +258,15 @@ def ao_hbm_copy(src, dst, n: int, nontemporal: bool = False, stream=None) -> Non
     _check(lib.ao_hbm_copy(_ptr(src), _ptr(dst), n, 1 if nontemporal else 0, _stream(stream)))
 
 
+def gather_probe_out_len(m: int) -> int:
+    """Doubles ao_gather_probe writes for m indices."""
+    return 4 * ((m + 2047) // 2048)
+
+
+def ao_gather_probe(idx, x, m: int, nx: int, out, stream=None) -> None:
+    _check(lib.ao_gather_probe(_ptr(idx), _ptr(x), m, nx, _ptr(out), _stream(stream)))
+
+
 def ao_device_cus() -> int:
     return lib.ao_device_cus()
 
@@ -283,6 +294,13 @@ def batch_info(batch):
     tiles = (ctypes.c_int * 15)()
     _check(lib.batch_info(batch, inst, items, tiles))
     return list(inst), list(items), [tuple(tiles[3 * b:3 * b + 3]) for b in range(5)]
+
+
+def batch_min_traffic(batch) -> float:
+    """Least HBM bytes one batch_run moves with the tiles in use."""
+    out = ctypes.c_double(0.0)
+    _check(lib.batch_min_traffic(batch, ctypes.byref(out)))
+    return out.value
 
 
 def batch_candidates():

@@ -668,6 +668,20 @@ int batch_info(const ao_batch* b, int* instances, int* items, int* tiles_xyz) {
     return AO_OK;
 }
 
+int batch_min_traffic(const ao_batch* b, double* bytes) {
+    if (!b || !bytes) return fail(AO_EINVAL, "batch or bytes is NULL");
+    double t = 0.0;
+    for (size_t q = 0; q < b->insts.size(); ++q) {
+        const Inst& in = b->insts[q];
+        const double n = (double)in.nx * in.ny * in.nz;
+        const int kind = kCands[b->cand[b->bucket[q]]].kind;
+        // a zero-sweep instance is one copy: 16 B per point as well
+        t += 16.0 * n * (in.sweeps == 0 ? 1 : passes_of(in.sweeps, kind));
+    }
+    *bytes = t;
+    return AO_OK;
+}
+
 int batch_candidates(int* tiles) {
     if (tiles)
         for (int c = 0; c < kNumCands; ++c) {

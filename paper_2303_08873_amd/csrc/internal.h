@@ -96,6 +96,12 @@ hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const 
                     const double* x, double* y, hipStream_t s, const SpmvEpi& ep = SpmvEpi(),
                     bool values_ready = false);
 
+// Gather probe: out[w] = sum of x[idx[k]] over the entries of wave w
+// (idx clamped into [0, nx)); out holds gather_probe_out_len(m) doubles.
+int64_t gather_probe_out_len(int64_t m);
+hipError_t gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, double* out,
+                        hipStream_t s);
+
 // Cost model kernels.
 struct MlpNorm {
     float mu[AO_MAX_FEATURES];

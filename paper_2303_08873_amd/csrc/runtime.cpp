@@ -501,6 +501,101 @@ int run_cosched(ao_region* r, const ao_variant& v, const ao_args* a, hipStream_t
     return AO_OK;
 }
 
+// The GPU launch plan of a Jacobi variant for S sweeps: one launch per
+// sweep, or (families fusing P = 2, 3 or 4 sweeps per pass) one per P
+// sweeps, the S mod P remaining sweeps first as one single register
+// z-march sweep, one two-sweep or one three-sweep pass.  The one-point-per-
+// thread family runs a grid of at most 8192 points in one workgroup's LDS,
+// all S sweeps in one launch (only for a block shape its sweep kernel
+// accepts).
+struct JacobiPlan {
+    int P = 1;            // sweeps per full launch
+    int rem = 0;          // sweeps of the first launch when S mod P != 0
+    int launches = 0;     // 0 for S = 0
+    bool lds_all = false;
+};
+
+JacobiPlan jacobi_plan(const ao_variant& v, int nx, int ny, int nz, int S) {
+    JacobiPlan p;
+    p.P = v.family == AO_FAM_JACOBI_ZREG_T2   ? 2
+          : v.family == AO_FAM_JACOBI_ZREG_T3 ? 3
+          : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4
+                                              : 1;
+    p.rem = S % p.P;
+    p.lds_all = v.family == AO_FAM_JACOBI_DIRECT && S >= 1 && lds_sweeps_fit(nx, ny, nz) &&
+                v.bx > 0 && v.by > 0 && (int64_t)v.bx * v.by <= 1024 && (v.bx * v.by) % 64 == 0;
+    p.launches = S == 0 ? 0 : p.lds_all ? 1 : S / p.P + (p.rem ? 1 : 0);
+    return p;
+}
+
+// Launch l of the plan: src -> dst.
+hipError_t jacobi_launch(const ao_variant& v, const JacobiPlan& p, int l, const double* src,
+                         double* dst, int nx, int ny, int nz, int S, hipStream_t s) {
+    if (p.lds_all) return jacobi_gpu_lds_sweeps(src, dst, nx, ny, nz, S, s);
+    if (p.P == 1) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
+    // the first launch of a fused family takes the S mod P remaining sweeps
+    // with the largest row count per wave, not above the variant's, that
+    // its family is built for
+    if (l == 0 && p.rem > 0) {
+        if (p.rem == 1) {
+            const int rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
+            const ao_variant one{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, rows, v.bz,
+                                 v.flags & AO_VF_NT_STORE};
+            return jacobi_gpu_sweep(one, src, dst, nx, ny, nz, s);
+        }
+        if (p.rem == 2) {
+            int rows = v.by;
+            while (rows > 1 && !t2_rows_ok(rows)) --rows;
+            const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, rows, v.bz,
+                                 v.flags & AO_VF_NT_STORE};
+            return jacobi_gpu_double_sweep(two, src, dst, nx, ny, nz, s);
+        }
+        int rows = v.by;
+        while (rows > 1 && !t3_rows_ok(rows)) --rows;
+        const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, rows, v.bz,
+                               v.flags & AO_VF_NT_STORE};
+        return jacobi_gpu_multi_sweep(three, src, dst, nx, ny, nz, s);
+    }
+    return p.P == 2 ? jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s)
+                    : jacobi_gpu_multi_sweep(v, src, dst, nx, ny, nz, s);
+}
+
+// Enqueue S sweeps of GPU variant v from u0 into out (device buffers of N
+// doubles).  Launch k writes out when L-1-k is even and scratch otherwise,
+// so the last launch lands in out; scratch (N doubles) is read only after
+// a launch has written all of it and is unused when L <= 1.  S = 0 copies.
+hipError_t jacobi_gpu_resident(const ao_variant& v, const double* u0, double* out,
+                               double* scratch, int nx, int ny, int nz, int S, hipStream_t s) {
+    const size_t n = (size_t)nx * ny * nz;
+    if (n == 0) return hipSuccess;
+    if (S == 0) return hipMemcpyAsync(out, u0, n * 8, hipMemcpyDeviceToDevice, s);
+    const JacobiPlan p = jacobi_plan(v, nx, ny, nz, S);
+    if (p.launches > 1 && !scratch) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    const double* src = u0;
+    for (int k = 0; k < p.launches && e == hipSuccess; ++k) {
+        double* dst = ((p.launches - 1 - k) % 2 == 0) ? out : scratch;
+        e = jacobi_launch(v, p, k, src, dst, nx, ny, nz, S, s);
+        src = dst;
+    }
+    return e;
+}
+
+// The same, alternating between two device buffers a -> b -> a ...: the
+// result lands in b when the launch count is odd and in a otherwise (a
+// holds the input and is overwritten from the second launch on).
+hipError_t jacobi_gpu_swap(const ao_variant& v, double* a, double* b, int nx, int ny, int nz,
+                           int S, hipStream_t s, bool* in_b) {
+    const JacobiPlan p = jacobi_plan(v, nx, ny, nz, S);
+    *in_b = p.launches % 2 == 1;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < p.launches && e == hipSuccess; ++k) {
+        e = jacobi_launch(v, p, k, a, b, nx, ny, nz, S, s);
+        std::swap(a, b);
+    }
+    return e;
+}
+
 // Enqueue / run variant `vid` once.  When `sync` is set the call waits and
 // returns the time in *secs; otherwise GPU timings are left pending with
 // record index `rec` (host variants always return *secs).
@@ -518,72 +613,19 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
             if (rc) return rc;
             hipEvent_t e0 = get_event(r), e1 = get_event(r);
             if (!e0 || !e1) return fail(AO_EHIP, "event creation failed");
-            // launches: one per sweep, or (families fusing P = 2, 3 or 4
-            // sweeps per pass) one per P sweeps, the S mod P remaining sweeps
-            // first as one single register z-march sweep, one two-sweep or one
-            // three-sweep pass
-            const int P = v.family == AO_FAM_JACOBI_ZREG_T2   ? 2
-                          : v.family == AO_FAM_JACOBI_ZREG_T3 ? 3
-                          : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4
-                                                              : 1;
-            const int rem = S % P;
-            const int L = S / P + (rem ? 1 : 0);
-            // (each with the largest row count per wave, not above the
-            // variant's, that its family is built for)
-            const int single_rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
-            int two_rows = v.by, three_rows = v.by;
-            while (two_rows > 1 && !t2_rows_ok(two_rows)) --two_rows;
-            while (three_rows > 1 && !t3_rows_ok(three_rows)) --three_rows;
-            const ao_variant single{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, single_rows, v.bz,
-                                    v.flags & AO_VF_NT_STORE};
-            const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, two_rows, v.bz,
-                                 v.flags & AO_VF_NT_STORE};
-            const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, three_rows, v.bz,
-                                   v.flags & AO_VF_NT_STORE};
-            auto launch = [&](int l, const double* src, double* dst) {
-                if (P == 1) return jacobi_gpu_sweep(v, src, dst, nx, ny, nz, s);
-                if (l == 0 && rem == 1) return jacobi_gpu_sweep(single, src, dst, nx, ny, nz, s);
-                if (l == 0 && rem == 2) return jacobi_gpu_double_sweep(two, src, dst, nx, ny, nz, s);
-                if (l == 0 && rem == 3) return jacobi_gpu_multi_sweep(three, src, dst, nx, ny, nz, s);
-                return P == 2 ? jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s)
-                              : jacobi_gpu_multi_sweep(v, src, dst, nx, ny, nz, s);
-            };
-            // the one-point-per-thread family runs a grid of at most 8192
-            // points in one workgroup's LDS, all S sweeps in one launch
-            // (only for a block shape its sweep kernel accepts)
-            const bool lds_all = v.family == AO_FAM_JACOBI_DIRECT && S >= 1 &&
-                                 lds_sweeps_fit(nx, ny, nz) && v.bx > 0 && v.by > 0 &&
-                                 (int64_t)v.bx * v.by <= 1024 && (v.bx * v.by) % 64 == 0;
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess && n > 0) {
                 if (a->resident) {
-                    if (S == 0) {
-                        e = hipMemcpyAsync(a->out, a->u0, n * 8, hipMemcpyDeviceToDevice, s);
-                    } else if (lds_all) {
-                        e = jacobi_gpu_lds_sweeps(a->u0, a->out, nx, ny, nz, S, s);
-                    } else {
-                        const double* src = a->u0;
-                        for (int k = 0; k < L && e == hipSuccess; ++k) {
-                            double* dst = ((L - 1 - k) % 2 == 0) ? a->out : r->d_a;
-                            e = launch(k, src, dst);
-                            src = dst;
-                        }
-                    }
+                    e = jacobi_gpu_resident(v, a->u0, a->out, r->d_a, nx, ny, nz, S, s);
                 } else {
+                    // staged through the region's two device buffers
+                    bool in_b = false;
                     e = hipMemcpyAsync(r->d_a, a->u0, n * 8, hipMemcpyHostToDevice, s);
-                    double* p = r->d_a;
-                    double* q = r->d_b;
-                    if (lds_all) {
-                        if (e == hipSuccess) e = jacobi_gpu_lds_sweeps(p, q, nx, ny, nz, S, s);
-                        std::swap(p, q);
-                    } else {
-                        for (int k = 0; k < L && e == hipSuccess; ++k) {
-                            e = launch(k, p, q);
-                            std::swap(p, q);
-                        }
-                    }
+                    if (e == hipSuccess) e = jacobi_gpu_swap(v, r->d_a, r->d_b, nx, ny, nz, S, s,
+                                                             &in_b);
                     if (e == hipSuccess)
-                        e = hipMemcpyAsync(a->out, p, n * 8, hipMemcpyDeviceToHost, s);
+                        e = hipMemcpyAsync(a->out, in_b ? r->d_b : r->d_a, n * 8,
+                                           hipMemcpyDeviceToHost, s);
                 }
             }
             if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -1179,6 +1221,18 @@ int ao_hbm_copy(const double* src, double* dst, int64_t n, int nontemporal, void
         (void)hipGetLastError();
         return fail(e == hipErrorInvalidValue ? AO_EINVAL : AO_EHIP,
                     hip_msg("copy (buffers must be 16-byte aligned)", e));
+    }
+    return AO_OK;
+}
+
+int ao_gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, double* out,
+                    void* stream) {
+    if (m < 0 || nx <= 0 || (m > 0 && (!idx || !x || !out)))
+        return fail(AO_EINVAL, "bad arguments");
+    hipError_t e = gather_probe(idx, x, m, nx, out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AO_EHIP, hip_msg("gather probe", e));
     }
     return AO_OK;
 }

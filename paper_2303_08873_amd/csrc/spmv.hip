@@ -830,4 +830,53 @@ hipError_t spmv_banded(const ao_variant& v, SpmvPlan& p, const double* val, cons
     return spmv_merge_path(mv, p, nullptr, nullptr, x, y, s, ep, p.prod, b->bpos);
 }
 
+// ---- gather probe ------------------------------------------------------------
+//
+// The memory access of a gather-per-nonzero SpMV and nothing else: idx[k]
+// streamed once (non-temporal), x[idx[k]] gathered, the gathered values
+// summed per wave so that no load is dead.  Workgroup g covers the 2048
+// entries [2048 g, 2048 g + 2048); on a round-robin dispatch it runs on XCD
+// g % 8, so an index array whose chunk g only names columns of one slice
+// per XCD measures gathers that stay in that XCD's L2.
+
+namespace {
+
+constexpr int kProbeChunk = 2048;  // entries per workgroup (256 threads x 8)
+
+__global__ __launch_bounds__(256) void k_gather_probe(const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ x, int64_t m,
+                                                      int64_t nx, double* __restrict__ out) {
+    const int64_t lo = (int64_t)blockIdx.x * kProbeChunk;
+    constexpr int U = kProbeChunk / 256;
+    int32_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = lo + threadIdx.x + 256 * u;
+        const int32_t v = j < m ? __builtin_nontemporal_load(idx + j) : 0;
+        c[u] = (v >= 0 && v < nx) ? v : 0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = lo + threadIdx.x + 256 * u;
+        if (j < m) acc += x[c[u]];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) out[(int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)] = acc;
+}
+
+}  // namespace
+
+int64_t gather_probe_out_len(int64_t m) { return 4 * ((m + kProbeChunk - 1) / kProbeChunk); }
+
+hipError_t gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, double* out,
+                        hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const int64_t blocks = (m + kProbeChunk - 1) / kProbeChunk;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_gather_probe, dim3((unsigned)blocks), dim3(256), 0, s, idx, x, m, nx, out);
+    return hipGetLastError();
+}
+
 }  // namespace ao

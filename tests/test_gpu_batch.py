@@ -158,3 +158,22 @@ def test_three_sweep_tiles_of_different_rows_across_buckets(env, orc):
             torch.cuda.synchronize()
             _check(torch, bufs, refs, f"tiles {plan} graph={use_graph}")
     ao.batch_destroy(b)
+
+
+def test_min_traffic_counts_passes(env):
+    # 16 B per point per pass: one-point-per-thread tiles take S passes,
+    # three-sweep tiles ceil(S / 3) (the first pass takes S mod 3 sweeps)
+    ao, torch, dev, st = env
+    shapes = [(9, 10, 11), (40, 33, 20)]
+    sweeps = [5, 7]
+    ins, bufs = _instances(ao, torch, dev, shapes, sweeps, 900)
+    b = ao.batch_create(ins)
+    cands = ao.batch_candidates()
+    direct = next(c for c, t in enumerate(cands) if t[0] == 0)
+    tri = next(c for c, t in enumerate(cands) if t[0] in (21, 22, 24))
+    pts = [nx * ny * nz for nx, ny, nz in shapes]
+    ao.batch_set_tiles(b, [direct] * 5)
+    assert ao.batch_min_traffic(b) == 16.0 * (pts[0] * 5 + pts[1] * 7)
+    ao.batch_set_tiles(b, [tri] * 5)
+    assert ao.batch_min_traffic(b) == 16.0 * (pts[0] * 2 + pts[1] * 3)
+    ao.batch_destroy(b)

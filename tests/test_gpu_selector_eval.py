@@ -1,21 +1,25 @@
-"""The learned selector against the method without it, on a small instance
-of the evaluation pipeline: RoundRobin-profiled training runs, GPU
-training, an exhaustive held-out table.  The trained network must beat the
-untrained one and the static default, and selecting must cost at least 10x
-less than timing every variant."""
+"""The learned selector against its target on held-out shapes of the
+cost-model workload: per-axis dims log-uniform in [8, 512], sweeps 5 / 10 /
+20, data in device memory or in pinned host memory.  Training data are
+RoundRobin-profiled runs of the method itself, the network is trained by
+the library's GPU kernels, and an exhaustive table of held-out shapes
+(other seed) judges it.  Target: geometric-mean regret at most 5% of the
+exhaustive best, at a selection cost at least 10x below timing every
+variant; the trained network must also beat the untrained one and the
+static default (Sec. 2, Apollo paragraph; Sec. 4 evaluation)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_selector_gain():
-    # shapes up to 160 per side: large enough that the fastest variant
-    # depends on the shape (small grids alone are launch-bound, where every
-    # GPU variant times alike and the comparison would measure noise)
+def test_learned_selector_held_out_target():
     from paper_2303_08873_amd import evaluate
-    r = evaluate.run(n_train=160, n_test=80, max_dim=160, reps=5, epochs=200)
+    r = evaluate.run(n_train=1000, n_test=300, max_dim=512, reps=5, epochs=200)
     learned, untrained, static = r["learned"], r["untrained_net"], r["static_default"]
-    assert learned["geomean_regret_pct"] <= untrained["geomean_regret_pct"]
-    assert learned["geomean_regret_pct"] <= static["geomean_regret_pct"] + 1.0
-    assert learned["geomean_regret_pct"] <= 25.0
+    print(f"held-out geomean regret {learned['geomean_regret_pct']:.2f}% (static "
+          f"{static['geomean_regret_pct']:.2f}%, untrained {untrained['geomean_regret_pct']:.2f}%), "
+          f"selection cost ratio {r['selection_cost_ratio_median']:.1f}", flush=True)
+    assert learned["geomean_regret_pct"] <= 5.0
     assert r["selection_cost_ratio_median"] >= 10.0
+    assert learned["geomean_regret_pct"] < untrained["geomean_regret_pct"]
+    assert learned["geomean_regret_pct"] < static["geomean_regret_pct"]

@@ -178,3 +178,25 @@ def test_reused_buffers_same_n_and_nnz(env, orc):
             torch.cuda.synchronize()
             assert np.array_equal(y.cpu().numpy(), want), v
     ao.region_destroy(h)
+
+
+def test_gather_probe_sums(env):
+    # the probe's per-wave sums against the same gathers summed on the host:
+    # wave w of workgroup g covers entries 2048 g + 64 w' + 256 u (u = 0..7,
+    # w' = lane group of wave w); order differs, so compare within rounding
+    ao, torch, dev, st = env
+    n, m = 5000, 2048 * 3 + 700
+    rng = np.random.default_rng(3)
+    idx = rng.integers(-5, n + 5, size=m).astype(np.int32)  # a few out of range: read x[0]
+    x = rng.standard_normal(n)
+    out = torch.full((ao.gather_probe_out_len(m),), float("nan"), dtype=torch.float64, device=dev)
+    ti, tx = torch.from_numpy(idx).to(dev), torch.from_numpy(x).to(dev)
+    ao.ao_gather_probe(ti, tx, m, n, out, stream=st)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ic = np.where((idx >= 0) & (idx < n), idx, 0)
+    want = np.zeros(got.size)
+    for k in range(m):
+        g, t = divmod(k, 2048)
+        want[4 * g + (t % 256) // 64] += x[ic[k]]
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
