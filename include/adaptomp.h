@@ -222,6 +222,27 @@ int region_declare_variants(const char* model_name, int kind, const ao_variant* 
 int region_run(ao_region* r, const ao_args* a, const float* features, void* stream, int variant,
                int* chosen);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc:
+ * region_run of the named GPU variant (variant >= 0) of a Jacobi region
+ * on device-resident buffers that allocates nothing.  The array between
+ * the launches of one execution (needed when the variant takes more than
+ * one launch: more sweeps than it fuses) is a fixed device array of
+ * AO_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the region's own scratch.  No
+ * selection, profiling record or training takes place.  Enqueued on
+ * stream (of the current device); output bit-identical to region_run of
+ * the same variant.  AO_EINVAL, with nothing enqueued, for a grid whose
+ * execution needs more than AO_NOALLOC_SCRATCH_BYTES of scratch (more than
+ * AO_NOALLOC_SCRATCH_BYTES / 8 points and more than one launch), a host or
+ * co-scheduled variant, host-resident data, an SpMV region or a variant id
+ * < 0.  Every call on one GPU shares its array and leaves its contents
+ * behind: calls that overlap in time on one GPU (other streams or threads)
+ * race and must be serialised by the caller.  The array needs no clearing:
+ * each launch writes all of it before the next one reads it. */
+#define AO_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB: grids of up to 8,388,608 points */
+int region_run_noalloc(ao_region* r, const ao_args* a, void* stream, int variant);
+
 /* Record one execution that the caller ran itself (the consumer side of the
  * producer-consumer pattern: user code ran variant `variant` for these
  * features and took `seconds`) -- Table 1 __apollo_region_end.  Appends to

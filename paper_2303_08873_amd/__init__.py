@@ -21,7 +21,7 @@ from ._lib import (  # noqa: F401
     ao_mlp_grad, batch_autotune, batch_candidates, batch_create, batch_destroy, batch_info,
     batch_min_traffic, batch_run, batch_set_tiles,
     region_clear_memo, region_declare_variants, region_destroy, region_features, region_load, region_profile,
-    region_record, region_records, region_run, region_save, region_stats, selector_select, selector_train,
+    region_record, region_records, region_run, region_run_noalloc, region_save, region_stats, selector_select, selector_train,
     jacobi_args, relax_args, spmv_args)
 from .variants import (  # noqa: F401
     jacobi_variants_blocks, jacobi_variants_sweep, spmv_variants)

@@ -89,6 +89,7 @@ def _load():
         "region_declare_variants": [ctypes.c_char_p, I, P, I, I, ctypes.c_char_p, P],
         "region_run": [P, P, P, P, I, P],
         "region_record": [P, P, I, ctypes.c_double],
+        "region_run_noalloc": [P, P, P, I],
         "region_features": [P, P, P, P],
         "region_profile": [P, P, P, I, I, I, P, I, P],
         "selector_train": [P, P, P],
@@ -177,6 +178,12 @@ def region_run(region, args: Args, features=None, stream=None, variant: int = -1
     rc = _check(lib.region_run(region, ctypes.byref(args), fbuf, _stream(stream), variant,
                                ctypes.byref(chosen)))
     return rc, chosen.value
+
+
+def region_run_noalloc(region, args: Args, variant: int, stream=None) -> int:
+    """Run GPU variant `variant` without allocating (the library's static
+    scratch array); returns the status."""
+    return _check(lib.region_run_noalloc(region, ctypes.byref(args), _stream(stream), variant))
 
 
 def region_features(region, args: Args, stream=None) -> list:

@@ -1209,6 +1209,49 @@ const char kMagic[8] = {'A', 'O', 'M', 'P', 'D', 'B', 0, 1};
 
 // ==========================================================================
 // C ABI
+namespace ao {
+
+// Scratch of the allocation-free entry point: the ping-pong array between
+// the launches of one region execution.  One copy per GPU, held from the
+// library's first use of that GPU until the process ends.  Host code never
+// passes this name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = (size_t)AO_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AO_EHIP, hip_msg("current device", e));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(AO_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(AO_EHIP, hip_msg("static scratch address", e));
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return AO_OK;
+}
+
+}  // namespace
+}  // namespace ao
+
 // ==========================================================================
 extern "C" {
 
@@ -1387,6 +1430,47 @@ int region_run(ao_region* r, const ao_args* a, const float* features, void* stre
     if (chosen) *chosen = vid;
     maybe_train(r);
     return status;
+}
+
+int region_run_noalloc(ao_region* r, const ao_args* a, void* stream, int variant) {
+    if (!r) return fail(AO_EINVAL, "region is NULL");
+    std::lock_guard<std::mutex> g(r->mu);
+    int rc = validate_args(r, a);
+    if (rc) return rc;
+    if (r->kind != AO_JACOBI7_F64)
+        return fail(AO_EINVAL, "region_run_noalloc runs Jacobi regions only");
+    if (variant < 0 || variant >= (int)r->variants.size())
+        return fail(AO_EINVAL, "variant id out of range (the caller names the variant)");
+    const ao_variant& v = r->variants[variant];
+    if (v.target != AO_TARGET_GPU || v.family == AO_FAM_JACOBI_COSCHED)
+        return fail(AO_EINVAL, "region_run_noalloc runs GPU variants only");
+    if (a->resident != 1) return fail(AO_EINVAL, "region_run_noalloc needs device-resident buffers");
+    if (r->failed_mask & (1 << variant))
+        return fail(AO_ELAUNCH, "variant " + std::to_string(variant) + " is masked out (failed launch)");
+    void* sp = nullptr;
+    rc = noalloc_scratch(&sp);
+    if (rc) return rc;
+    const int nx = a->nx, ny = a->ny, nz = a->nz, S = a->sweeps;
+    const size_t n = (size_t)nx * ny * nz;
+    if (n == 0) return AO_OK;
+    if (jacobi_plan(v, nx, ny, nz, S).launches > 1 && n * 8 > kNoallocScratchBytes)
+        return fail(AO_EINVAL, "grid of " + std::to_string(n) + " points needs " +
+                                   std::to_string(n * 8) + " bytes of scratch, above the " +
+                                   std::to_string(kNoallocScratchBytes) +
+                                   "-byte static array of region_run_noalloc");
+    hipError_t e = jacobi_gpu_resident(v, a->u0, a->out, (double*)sp, nx, ny, nz, S,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (e == hipErrorInvalidConfiguration || e == hipErrorInvalidValue ||
+            e == hipErrorLaunchFailure) {
+            r->failed_mask |= 1 << variant;
+            return fail(AO_ELAUNCH, "variant " + std::to_string(variant) +
+                                        " cannot launch (masked out): " + hipGetErrorString(e));
+        }
+        return fail(AO_EHIP, hip_msg("GPU variant", e));
+    }
+    return AO_OK;
 }
 
 int region_features(ao_region* r, const ao_args* a, void* stream, float* features) {
