@@ -154,17 +154,33 @@ def blocks_workload(steps: int, warmup: int):
         "note": "4 MiB per array: cache-resident and launch-bound"}), flush=True)
 
 
+JACOBI_SOURCES = ("jacobi.hip", "zmarch.h", "lanes.h")
+BATCH_SOURCES = ("batch.hip", "zmarch.h", "lanes.h")
+
+
+def source_digest(names):
+    """SHA-256 over the kernel sources a counter summary was taken with: a
+    summary whose digest differs describes another kernel and is not used."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2303_08873_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def pmc_traffic(variant_key):
     """HBM bytes per launch of the dominant kernel from the committed
     counter summary (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, scaled by the
-    copy-probe calibration), when it was taken for this kernel."""
+    copy-probe calibration), when it was taken for this kernel and these
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", "jacobi_512_pmc.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("variant") != variant_key:
+    if d.get("variant") != variant_key or d.get("source_sha256") != source_digest(JACOBI_SOURCES):
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -191,10 +207,10 @@ def synth_u01(torch, dev, n):
     return synth.u01_torch(4242, n, dev)
 
 
-def kernel_only(variant: int, launches: int = 3):
-    """Counter runs: the size-sweep variant `variant` at 512^3 x 20 sweeps,
-    `launches` region executions, then 5 copies of 512^3 doubles (the
-    calibration kernel of known traffic)."""
+def kernel_only(variant: int, launches: int = 5):
+    """Counter and trace runs: the size-sweep variant `variant` at 512^3 x
+    20 sweeps, `launches` region executions, then 5 copies of 512^3 doubles
+    (the calibration kernel of known traffic)."""
     import torch
 
     import paper_2303_08873_amd as ao
@@ -218,6 +234,46 @@ def kernel_only(variant: int, launches: int = 3):
                       "copies": 5, "copy_bytes_each": 16 * n ** 3}), flush=True)
 
 
+# the variant the learned selector picks at each size of the sweep (the
+# exhaustive best as well in the recorded runs); the trace mode replays them
+SWEEP_PICKS = {16: 1, 32: 0, 64: 1, 128: 4, 256: 2, 512: 3}
+
+
+def trace_steps(steps: int, warmup: int):
+    """Trace run of the timed loop: `warmup` + `steps` size-sweep steps (one
+    region run per size, 20 sweeps, the variants of SWEEP_PICKS, the same
+    grids and order as the timed steps), then 5 copies of 512^3 doubles
+    (the calibration kernel of known traffic).  Under rocprofv3 the average
+    duration of the 512^3 kernel is comparable to the line's per-launch
+    time, which comes from the same loop."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    region = ao.region_declare_variants("bench_trace_steps", ao.AO_JACOBI7_F64,
+                                        ao.jacobi_variants_sweep(), model_type="roundrobin")
+    grids = {}
+    for n in SIZES:
+        u0 = synth.grid_u01_torch(n, n, n, seed=2000 + int(math.log2(n)), device=dev)
+        grids[n] = (u0, torch.empty_like(u0))
+    torch.cuda.synchronize()
+    for _ in range(warmup + steps):
+        for n in SIZES:
+            u0, out = grids[n]
+            ao.region_run(region, ao.jacobi_args(u0, out, n, n, n, SWEEPS), stream=stream,
+                          variant=SWEEP_PICKS[n])
+    torch.cuda.synchronize()
+    u0, _ = grids[SIZES[-1]]
+    b = torch.empty_like(u0)
+    for _ in range(5):
+        ao.ao_hbm_copy(u0, b, SIZES[-1] ** 3, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"trace_steps": steps, "warmup": warmup, "picks": SWEEP_PICKS,
+                      "copies": 5, "copy_bytes_each": 16 * SIZES[-1] ** 3}), flush=True)
+
+
 def batch_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     """The batched-instances line on its own (see batch_measure)."""
     print(json.dumps(batch_measure(steps, warmup, no_cpu_baseline)), flush=True)
@@ -233,7 +289,49 @@ def batch_pmc_traffic():
             d = json.load(fh)
     except (OSError, ValueError):
         return None
+    if d.get("source_sha256") != source_digest(BATCH_SOURCES):
+        return None
     return d.get("traffic_bytes_per_replay")
+
+
+def batch_kernel_only(replays: int = 5):
+    """Counter runs of the batched launch: the 256-grid workload (seed 3, 5
+    sweeps), autotuned, then a marker copy of 1024 doubles, `replays`
+    replays of the captured graph, and 5 copies of 512^3 doubles (the
+    calibration kernel).  The replays are the batch-kernel dispatches after
+    the marker."""
+    import torch
+
+    import paper_2303_08873_amd as ao
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    shapes = synth.batch_shapes(256, 8, 256, seed=3)
+    ins, bufs = [], []
+    for q, (nx, ny, nz) in enumerate(shapes):
+        u0 = synth.grid_u01_torch(int(nx), int(ny), int(nz), seed=3000 + q, device=dev)
+        out = torch.empty_like(u0)
+        bufs.append((u0, out))
+        ins.append(ao.jacobi_args(u0, out, int(nx), int(ny), int(nz), 5))
+    b = ao.batch_create(ins)
+    chosen = ao.batch_autotune(b, stream=stream, warmup=1, reps=3)
+    ao.batch_run(b, stream=stream, use_graph=True)  # capture
+    torch.cuda.synchronize()
+    mark = torch.zeros(2048, dtype=torch.float64, device=dev)
+    ao.ao_hbm_copy(mark[:1024], mark[1024:], 1024, stream=stream)
+    for _ in range(replays):
+        ao.batch_run(b, stream=stream, use_graph=True)
+    torch.cuda.synchronize()
+    min_bytes = ao.batch_min_traffic(b)
+    ao.batch_destroy(b)
+    big = synth.u01_torch(4242, 512 ** 3, dev)
+    dst = torch.empty_like(big)
+    for _ in range(5):
+        ao.ao_hbm_copy(big, dst, 512 ** 3, stream=stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"batch_kernel_only": True, "replays": replays, "autotuned": chosen,
+                      "min_traffic_bytes_per_replay": min_bytes, "copies": 5,
+                      "copy_bytes_each": 16 * 512 ** 3}), flush=True)
 
 
 def batch_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
@@ -334,9 +432,10 @@ def batch_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
 def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     """FP64 CSR SpMV region, n = 2^22 rows, Pareto-tail rows (index 1.5, mean
     16, max 4096), seed 5; 9 variants {thread-row, wave-row, merge-path} x
-    {64, 256, 1024}.  The cost model is trained on profiled matrices of other
+    {64, 256, 1024} and the x-slice family.  The cost model is trained on profiled matrices of other
     sizes and row-length laws (n 2^14..2^22, tail 1.2/1.5/2/3, mean 4/16/64,
     seeds 50+), then chooses on held-out matrices (2^21 and the 2^22 target);
+    the x-slice family (8K- and 16K-column slices) makes variants 9 and 10;
     regret against their exhaustive tables.  Prints one JSON line."""
     import torch
 
@@ -344,8 +443,9 @@ def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     import synth
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    V = 9
-    region = ao.region_declare_variants("bench_spmv", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
+    V = 11
+    region = ao.region_declare_variants("bench_spmv", ao.AO_CSR_SPMV_F64,
+                                        ao.spmv_variants(xslice=(13, 14)),
                                         min_train_data=10 ** 9, model_type="mlp")
 
     def load(n, seed, tail=1.5, mean=16.0):
@@ -353,7 +453,8 @@ def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
         t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
         y = torch.empty(n, dtype=torch.float64, device=dev)
         nnz = int(m["col"].size)
-        return t, y, ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz), nnz
+        return t, y, ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz,
+                                  values_id=1), nnz
 
     t0 = time.perf_counter()
     seed = 50
@@ -410,7 +511,7 @@ def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
            "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
            "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
            "held_out": rows}
-    v = ao.spmv_variants()[chosen]
+    v = ao.spmv_variants(xslice=(13, 14))[chosen]
     res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
                        "traffic": None,
@@ -474,23 +575,33 @@ def spmv_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
     t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     nnz = int(m["col"].size)
-    variants = ao.spmv_variants()
+    variants = ao.spmv_variants(xslice=(13, 14))
     V = len(variants)
     region = ao.region_declare_variants("bench_spmv_table", ao.AO_CSR_SPMV_F64, variants,
                                         min_train_data=10 ** 9, model_type="exhaustive")
-    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz)
+    # the matrix keeps its values through the timed calls: one values id
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz, values_id=1)
     med = ao.region_profile(region, a, warmup=1, reps=5, stream=stream, num_variants=V)
     best = min(range(V), key=lambda v: med[v])
-    for _ in range(warmup):
-        ao.region_run(region, a, stream=stream, variant=best)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        ao.region_run(region, a, stream=stream, variant=best)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / steps * 1e-3
+
+    def timed(args, v):
+        for _ in range(warmup):
+            ao.region_run(region, args, stream=stream, variant=v)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ao.region_run(region, args, stream=stream, variant=v)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps * 1e-3
+    sec = timed(a, best)
+    # the x-slice family when every call brings new values (values id 0:
+    # the values are reordered on every call)
+    a0 = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, nnz,
+                      structure_id=a.structure_id, values_id=0)
+    xs_ids = [v for v in range(V) if variants[v].family == ao.FAM_SPMV_XSLICE]
+    xs_fresh = {str(variants[v].by): timed(a0, v) for v in xs_ids}
     ao.region_destroy(region)
     byt = 12 * nnz + 4 * (n + 1) + 16 * n
     probes = gather_probes(ao, torch, stream, t["col"], t["x"], n)
@@ -504,6 +615,9 @@ def spmv_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
            "gather_probe_col_us": round(probes["col_us"], 2),
            "gather_probe_xcd_slice_us": round(probes["xcd_slice_us"], 2),
            "time_over_gather_probe_col": round(sec * 1e6 / probes["col_us"], 3),
+           "xslice_us_values_reordered_every_call": {k: round(v * 1e6, 2)
+                                                     for k, v in xs_fresh.items()},
+           "variants": [f"family={x.family} bx={x.bx} by={x.by}" for x in variants],
            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                         "kernel": f"variant {best} (family={v.family} bx={v.bx} by={v.by}) "
@@ -533,9 +647,10 @@ def relax_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     import synth
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    V = 9
+    V = 11
     omega, S = 2.0 / 3.0, 10
-    region = ao.region_declare_variants("bench_relax", ao.AO_CSR_RELAX_F64, ao.spmv_variants(),
+    region = ao.region_declare_variants("bench_relax", ao.AO_CSR_RELAX_F64,
+                                        ao.spmv_variants(xslice=(13, 14)),
                                         min_train_data=10 ** 9, model_type="mlp")
 
     def load(n, seed, tail, mean, sweeps):
@@ -544,7 +659,7 @@ def relax_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
         y = torch.empty(n, dtype=torch.float64, device=dev)
         nnz = int(m["col"].size)
         a = ao.relax_args(t["row_ptr"], t["col"], t["val"], t["x"], y, t["b"], t["d"], omega,
-                          sweeps, n, nnz)
+                          sweeps, n, nnz, values_id=1)
         return t, y, a, nnz
 
     t0 = time.perf_counter()
@@ -605,7 +720,7 @@ def relax_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
            "variant_gbs_at_target": [round(byt / x / 1e9, 1) for x in med],
            "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
            "held_out": rows}
-    v = ao.spmv_variants()[chosen]
+    v = ao.spmv_variants(xslice=(13, 14))[chosen]
     res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
                        "traffic": None,
@@ -698,8 +813,9 @@ def cosched_workload(steps: int, warmup: int):
 
 def spmv_kernel_only(variant: int, launches: int = 5):
     """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
-    executions.  Ids 0..8 are the benchmark's table; 9 and 10 are the banded
-    family (merge-path block 256 with 16 and with 8 column bands)."""
+    executions.  Ids 0..8 are {thread-row, wave-row, merge-path} x {64, 256,
+    1024}; 9 and 10 the x-slice family with 8K- and 16K-column slices (the
+    values reordered once: the matrix keeps one values id)."""
     import torch
 
     import paper_2303_08873_amd as ao
@@ -711,9 +827,10 @@ def spmv_kernel_only(variant: int, launches: int = 5):
     t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
     y = torch.empty(n, dtype=torch.float64, device=dev)
     region = ao.region_declare_variants("bench_spmv_kernel_only", ao.AO_CSR_SPMV_F64,
-                                        ao.spmv_variants(banded=((256, 16), (256, 8))),
+                                        ao.spmv_variants(xslice=(13, 14)),
                                         model_type="roundrobin")
-    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size),
+                     values_id=1)
     for _ in range(launches):
         ao.region_run(region, a, stream=stream, variant=variant)
     torch.cuda.synchronize()
@@ -728,14 +845,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=None,
-                    help="counter-collection mode: run one size-sweep variant at 512^3 only")
+                    help="counter-collection mode: one size-sweep variant at 512^3 only; with "
+                         "--workload spmv one SpMV variant on the 2^22 matrix; with --workload "
+                         "batch the autotuned graph of the batched workload")
+    ap.add_argument("--trace-steps", action="store_true",
+                    help="trace mode: the timed size-sweep loop with fixed variant picks only")
     ap.add_argument("--workload", default="size-sweep",
                     choices=["size-sweep", "batch", "spmv", "relax", "cosched", "blocks"],
                     help="size-sweep: the headline line; the others: the other region lines")
     args = ap.parse_args()
+    if args.trace_steps:
+        trace_steps(args.steps, args.warmup)
+        return
     if args.kernel_only is not None:
         if args.workload == "spmv":
             spmv_kernel_only(args.kernel_only)
+        elif args.workload == "batch":
+            batch_kernel_only()
         else:
             kernel_only(args.kernel_only)
         return

@@ -111,11 +111,17 @@ enum ao_family {
     AO_FAM_SPMV_THREAD_ROW = 10, /* GPU: one thread per row, blocks of bx */
     AO_FAM_SPMV_WAVE_ROW = 11,   /* GPU: by lanes (power of 2 <= 64, 0 = 64) per row, blocks of bx */
     AO_FAM_SPMV_MERGE_PATH = 12, /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
-    AO_FAM_SPMV_BANDED = 13      /* GPU: columns cut into by (8|16|32; 0 = 16) bands so that
-                                    each XCD gathers x from a slice held in its L2: the
-                                    values are copied band-major, products are formed band
-                                    by band, then summed per row by merge-path (blocks of
-                                    bx); a per-matrix plan of about 20 B per nonzero */
+    AO_FAM_SPMV_XSLICE = 13      /* GPU: columns cut into slices of 2^by columns (by 13|14;
+                                    0 = 14: 64 or 128 KB of x) and rows into blocks of at most
+                                    4096 nonzeros + rows; a per-matrix plan orders the
+                                    nonzeros slice by slice (about 8 B per nonzero plus 16 B
+                                    per nonzero of value and product arrays); per execution
+                                    the values are copied into that order when they changed
+                                    (see values_id), each slice's products are formed with x
+                                    in LDS, and each row block sums its rows from the
+                                    products in LDS; bx = 0 (fixed geometry); rows longer
+                                    than 4097 nonzeros are refused (AO_ELAUNCH, the variant
+                                    is masked for the region) */
 };
 
 /* variant flags */
@@ -166,6 +172,13 @@ typedef struct ao_args {
      * buffer, an edited matrix).  0 = unknown: the plan is rebuilt on every
      * call. */
     uint64_t structure_id;
+    /* Identity of the values (the contents of val) under that structure:
+     * families that keep the values in an order of their own
+     * (AO_FAM_SPMV_XSLICE) reuse that copy while values_id, structure_id
+     * and val are unchanged.  The caller gives new values a new id; 0 =
+     * unknown: the copy is refreshed on every call (within one relaxation
+     * execution it is made once for all sweeps). */
+    uint64_t values_id;
     /* Relaxation (AO_CSR_RELAX_F64; x, y, the matrix and sweeps as above):
      * right-hand side b[n], diagonal diag[n], weight omega. */
     const double* b;

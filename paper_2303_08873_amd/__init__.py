@@ -16,7 +16,7 @@ from ._lib import (  # noqa: F401
     FAM_JACOBI_DIRECT,
     FAM_JACOBI_HOST, FAM_JACOBI_ZMARCH, FAM_JACOBI_ZREG, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
     FAM_JACOBI_ZREG_T4, FAM_JACOBI_COSCHED,
-    FAM_SPMV_BANDED, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, AdaptError, Args, Stats,
+    FAM_SPMV_XSLICE, FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, AdaptError, Args, Stats,
     TrainOpts, Variant, lib, lib_path, ao_last_error, ao_device_cus, ao_gather_probe, ao_hbm_copy, gather_probe_out_len, ao_mlp_adam, ao_mlp_forward,
     ao_mlp_grad, batch_autotune, batch_candidates, batch_create, batch_destroy, batch_info,
     batch_min_traffic, batch_run, batch_set_tiles,

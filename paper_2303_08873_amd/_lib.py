@@ -18,7 +18,7 @@ FAM_JACOBI_ZREG_T2 = 4
 FAM_JACOBI_ZREG_T3 = 5
 FAM_JACOBI_ZREG_T4 = 6
 FAM_JACOBI_COSCHED = 7
-FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH, FAM_SPMV_BANDED = 10, 11, 12, 13
+FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH, FAM_SPMV_XSLICE = 10, 11, 12, 13
 AO_VF_NT_STORE = 1
 AO_VF_HALO_PREFETCH = 2
 AO_VF_OCCUPANCY = 4
@@ -52,7 +52,7 @@ class Args(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
-                ("structure_id", ctypes.c_uint64),
+                ("structure_id", ctypes.c_uint64), ("values_id", ctypes.c_uint64),
                 ("b", ctypes.c_void_p), ("diag", ctypes.c_void_p), ("omega", ctypes.c_double)]
 
 
@@ -352,12 +352,17 @@ def jacobi_args(u0, out, nx: int, ny: int, nz: int, sweeps: int, resident: int =
 _structure_ids = itertools.count(1)
 
 
-def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int, structure_id: int | None = None) -> Args:
+def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int, structure_id: int | None = None,
+              values_id: int = 0) -> Args:
     """Arguments of one SpMV execution.  Unless given, every call issues a
     fresh structure id, so the library's per-matrix plan is shared by the
-    executions that reuse this Args object and never by another matrix."""
+    executions that reuse this Args object and never by another matrix.
+    values_id (0 = unknown) names the contents of val: a nonzero id lets
+    the x-slice family reuse its reordered copy of the values while the id
+    stays the same; give changed values a new id."""
     a = Args()
     a.structure_id = next(_structure_ids) if structure_id is None else structure_id
+    a.values_id = int(values_id)
     a.kind = AO_CSR_SPMV_F64
     a.resident = 1
     a.row_ptr, a.col, a.val, a.x, a.y = _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y)
@@ -366,11 +371,11 @@ def spmv_args(row_ptr, col, val, x, y, n: int, nnz: int, structure_id: int | Non
 
 
 def relax_args(row_ptr, col, val, x, y, b, diag, omega: float, sweeps: int, n: int, nnz: int,
-               structure_id: int | None = None) -> Args:
+               structure_id: int | None = None, values_id: int = 0) -> Args:
     """Arguments of one weighted-Jacobi relaxation execution (S sweeps of
-    x <- x + omega (b - A x) / diag from x into y); structure ids as for
-    spmv_args."""
-    a = spmv_args(row_ptr, col, val, x, y, n, nnz, structure_id)
+    x <- x + omega (b - A x) / diag from x into y); structure and values
+    ids as for spmv_args."""
+    a = spmv_args(row_ptr, col, val, x, y, n, nnz, structure_id, values_id)
     a.kind = AO_CSR_RELAX_F64
     a.b, a.diag, a.omega, a.sweeps = _ptr(b), _ptr(diag), float(omega), int(sweeps)
     return a

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libadaptomp.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["jacobi.hip", "spmv.hip", "mlp.hip", "batch.hip", "runtime.cpp", "capi_mlp.cpp",
+HIP_SOURCES = ["jacobi.hip", "spmv.hip", "spmv_xslice.hip", "mlp.hip", "batch.hip", "runtime.cpp", "capi_mlp.cpp",
                "dtree.cpp"]
 HOST_SOURCES = ["host_jacobi.cpp"]
 

@@ -60,26 +60,38 @@ struct SpmvPlan {
         int32_t* sunit = nullptr;   // [blocks + 1] start unit within that row
     };
     std::vector<MergeSplit> mp;
-    // banded: columns cut into nb bands; every nonzero gets a place in a
-    // band-major copy (band outer, row inner, row order kept inside a row)
-    struct Banding {
-        int nb = 0;
-        int32_t* bstart = nullptr;  // [nb*n + 1] first band-major place of (band b, row i) at b*n+i
-        int32_t* bcol = nullptr;    // [nnz] column of each band-major place
-        int32_t* bpos = nullptr;    // [nnz] band-major place of CSR entry k
-        std::vector<int64_t> off;   // [nb + 1] first place of each band (host copy)
-        int chunks = 0;             // products workgroups per band (the largest band)
-        int32_t kbeg = 0;           // row_ptr[0]: places count from this CSR entry
+    // x-slice family: columns cut into slices of 2^swl columns, rows into
+    // blocks of at most 4096 cost units (nonzeros + rows); places ordered
+    // slice, block, CSR order
+    struct XSlice {
+        int swl = 0;                    // log2 of the slice width
+        int ns = 0, nb = 0;             // slices, row blocks
+        int64_t ncols = 0;              // columns (largest index + 1)
+        int32_t* rb = nullptr;          // [nb + 1] first row of each block
+        int32_t* off = nullptr;         // [ns*nb + 1] first place of piece (slice s, block t) at s*nb+t
+        int32_t* unit_ptr = nullptr;    // [n + 1] first 64-leaf unit of each row
+        int32_t* chunk_first = nullptr; // [ns + 1] first products chunk of each slice
+        int chunks = 0;
+        uint16_t* bcol = nullptr;       // [places] column inside the slice
+        uint16_t* bk = nullptr;         // [places] nonzero index inside the row block
+        uint32_t* uinfo = nullptr;      // [units] row inside its block << 16 | unit index in the row
+        double* bval = nullptr;         // [places] values in place order
+        double* prod = nullptr;         // [places] products in place order
+        int64_t units = 0, places = 0;
+        uint64_t values_id = 0;         // values_id of the values bval holds (0: none)
+        const double* values_of = nullptr;  // and the array they came from
+        void release();
     };
-    std::vector<Banding> bands;
-    double* bval = nullptr;  // [nnz] band-major values (refreshed per execution)
-    double* prod = nullptr;  // [nnz] band-major products
+    std::vector<XSlice> xs;
     ~SpmvPlan();
 };
 // Build the merge-path partition for workgroups of B threads (synchronises).
 hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s);
-// Build the banding with nb bands (synchronises); needs the plan's col array.
-hipError_t spmv_prepare_banded(SpmvPlan& p, int nb, const int32_t* col, hipStream_t s);
+// Build the x-slice plan for slices of 2^swl columns (synchronises); needs
+// the plan's col array and the longest row (features); rows longer than
+// spmv_xslice_max_row() nonzeros give hipErrorInvalidConfiguration.
+hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStream_t s);
+int spmv_xslice_max_row();
 
 hipError_t spmv_features(SpmvPlan& p, hipStream_t s);
 // What a finished row i with canonical sum s_i stores: y_i = s_i (b ==
@@ -89,9 +101,11 @@ struct SpmvEpi {
     const double* d = nullptr;
     double omega = 0.0;
 };
-// values_ready: the banded family's band-major copy of val already holds
-// this val (set by the caller for the second and later sweeps of one
-// execution); other families ignore it.
+// values_ready: the x-slice family's copy of val in place order already
+// holds this val (the caller knows it: the second and later sweeps of one
+// execution, or an unchanged values id); other families ignore it.
+hipError_t spmv_xslice(const ao_variant& v, SpmvPlan& p, const double* val, const double* x,
+                       double* y, hipStream_t s, const SpmvEpi& ep, bool values_ready);
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
                     const double* x, double* y, hipStream_t s, const SpmvEpi& ep = SpmvEpi(),
                     bool values_ready = false);

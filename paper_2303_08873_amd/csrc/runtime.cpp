@@ -215,12 +215,13 @@ int validate_variant(int kind, const ao_variant& v, int id) {
     if (kind == AO_CSR_SPMV_F64 || kind == AO_CSR_RELAX_F64) {
         if (v.target != AO_TARGET_GPU) return fail(AO_EINVAL, at + "SpMV variants run on the GPU");
         if (v.family != AO_FAM_SPMV_THREAD_ROW && v.family != AO_FAM_SPMV_WAVE_ROW &&
-            v.family != AO_FAM_SPMV_MERGE_PATH && v.family != AO_FAM_SPMV_BANDED)
+            v.family != AO_FAM_SPMV_MERGE_PATH && v.family != AO_FAM_SPMV_XSLICE)
             return fail(AO_EINVAL, at + "unknown SpMV family");
-        if (v.family == AO_FAM_SPMV_BANDED &&
-            ((v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) ||
-             (v.by != 0 && v.by != 8 && v.by != 16 && v.by != 32)))
-            return fail(AO_EINVAL, at + "banded SpMV needs bx 64..1024 (power of 2), by 0|8|16|32");
+        if (v.family == AO_FAM_SPMV_XSLICE) {
+            if (v.bx != 0 || (v.by != 0 && v.by != 13 && v.by != 14))
+                return fail(AO_EINVAL, at + "x-slice SpMV needs bx 0, by 0|13|14");
+            return AO_OK;
+        }
         if (v.bx <= 0) return fail(AO_EINVAL, at + "block size must be positive");
         if (v.family == AO_FAM_SPMV_WAVE_ROW && v.by != 0 &&
             (v.by < 1 || v.by > 64 || (v.by & (v.by - 1))))
@@ -371,18 +372,27 @@ SpmvPlan* get_plan(ao_region* r, const ao_args* a, hipStream_t s, int* rc) {
         return nullptr;
     }
     p->have_features = true;
-    // merge-path partitions for the region's merge-path and banded variants,
-    // and the banded variants' band plans
+    // merge-path partitions for the region's merge-path variants and the
+    // x-slice variants' plans (a matrix an x-slice plan cannot take -- a row
+    // above its limit, too many slices -- leaves that plan out: the variant
+    // then fails to launch and is masked)
     for (const ao_variant& v : r->variants) {
-        if ((v.family != AO_FAM_SPMV_MERGE_PATH && v.family != AO_FAM_SPMV_BANDED) || p->n <= 0)
+        if (p->n <= 0) continue;
+        if (v.family == AO_FAM_SPMV_XSLICE) {
+            e = spmv_prepare_xslice(*p, v.by == 0 ? 14 : v.by, a->col, s);
+            if (e == hipErrorInvalidConfiguration) {
+                (void)hipGetLastError();
+                continue;
+            }
+        } else if (v.family == AO_FAM_SPMV_MERGE_PATH) {
+            if (v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) continue;
+            e = spmv_prepare_merge(*p, v.bx, s);
+        } else {
             continue;
-        if (v.bx != 64 && v.bx != 128 && v.bx != 256 && v.bx != 512 && v.bx != 1024) continue;
-        e = spmv_prepare_merge(*p, v.bx, s);
-        if (e == hipSuccess && v.family == AO_FAM_SPMV_BANDED)
-            e = spmv_prepare_banded(*p, v.by == 0 ? 16 : v.by, a->col, s);
+        }
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            *rc = fail(AO_EHIP, hip_msg("merge-path / band plan", e));
+            *rc = fail(AO_EHIP, hip_msg("merge-path / x-slice plan", e));
             return nullptr;
         }
     }
@@ -702,9 +712,21 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
     if (!p) return rc;
     hipEvent_t e0 = get_event(r), e1 = get_event(r);
     if (!e0 || !e1) return fail(AO_EHIP, "event creation failed");
+    // the x-slice family's reordered values are reused while the caller's
+    // values id (nonzero) and value array stay the same
+    SpmvPlan::XSlice* xq = nullptr;
+    if (v.family == AO_FAM_SPMV_XSLICE)
+        for (auto& q : p->xs)
+            if (q.swl == (v.by == 0 ? 14 : v.by)) xq = &q;
+    const bool cached = xq && a->values_id != 0 && xq->values_id == a->values_id &&
+                        xq->values_of == a->val;
+    if (xq) {
+        xq->values_id = 0;  // until this call's copy is enqueued
+        xq->values_of = nullptr;
+    }
     hipError_t e = hipEventRecord(e0, s);
     if (r->kind == AO_CSR_SPMV_F64) {
-        if (e == hipSuccess) e = spmv_gpu(v, *p, a->col, a->val, a->x, a->y, s);
+        if (e == hipSuccess) e = spmv_gpu(v, *p, a->col, a->val, a->x, a->y, s, SpmvEpi(), cached);
     } else {
         // relaxation: S sweeps ping-ponging between y and the region's
         // scratch so that the last one lands in y
@@ -727,9 +749,13 @@ int run_variant(ao_region* r, int vid, const ao_args* a, hipStream_t s, bool syn
         const double* src = a->x;
         for (int k = 0; k < S && e == hipSuccess; ++k) {
             double* dst = ((S - 1 - k) % 2 == 0) ? a->y : r->d_a;
-            e = spmv_gpu(v, *p, a->col, a->val, src, dst, s, ep, k > 0);
+            e = spmv_gpu(v, *p, a->col, a->val, src, dst, s, ep, cached || k > 0);
             src = dst;
         }
+    }
+    if (e == hipSuccess && xq && a->values_id != 0) {
+        xq->values_id = a->values_id;
+        xq->values_of = a->val;
     }
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e != hipSuccess) {
@@ -932,13 +958,7 @@ ao_region::~ao_region() {
 SpmvPlan::~SpmvPlan() {
     for (auto& m : mp)
         if (m.srow) hipFree(m.srow);
-    for (auto& b : bands) {
-        if (b.bstart) hipFree(b.bstart);
-        if (b.bcol) hipFree(b.bcol);
-        if (b.bpos) hipFree(b.bpos);
-    }
-    if (bval) hipFree(bval);
-    if (prod) hipFree(prod);
+    for (auto& q : xs) q.release();
     if (unit_ptr) hipFree(unit_ptr);
     if (unit_sums) hipFree(unit_sums);
 }

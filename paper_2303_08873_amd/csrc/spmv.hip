@@ -216,15 +216,13 @@ hipError_t spmv_features(SpmvPlan& p, hipStream_t s) {
 }
 
 hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep,
-                           const double* prod = nullptr, const int32_t* bpos = nullptr);
-hipError_t spmv_banded(const ao_variant& v, SpmvPlan& p, const double* val, const double* x,
-                       double* y, hipStream_t s, const SpmvEpi& ep, bool values_ready);
+                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep);
 
 hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
                     const double* x, double* y, hipStream_t s, const SpmvEpi& ep,
                     bool values_ready) {
     if (p.n <= 0) return hipSuccess;
+    if (v.family == AO_FAM_SPMV_XSLICE) return spmv_xslice(v, p, val, x, y, s, ep, values_ready);
     const int B = v.bx;
     if (B <= 0 || B > 1024 || B % 64 != 0) return hipErrorInvalidConfiguration;
     if (v.family == AO_FAM_SPMV_THREAD_ROW) {
@@ -254,7 +252,6 @@ hipError_t spmv_gpu(const ao_variant& v, SpmvPlan& p, const int32_t* col, const 
         return hipGetLastError();
     }
     if (v.family == AO_FAM_SPMV_MERGE_PATH) return spmv_merge_path(v, p, col, val, x, y, s, ep);
-    if (v.family == AO_FAM_SPMV_BANDED) return spmv_banded(v, p, val, x, y, s, ep, values_ready);
     return hipErrorInvalidValue;
 }
 
@@ -368,9 +365,7 @@ __global__ void k_partition(int n, int nb, int D, const int32_t* __restrict__ ro
 // The partition tables must describe this row_ptr (the runtime keys them on
 // the structure id); every index below is nevertheless clamped to its
 // buffer, so tables of another matrix give wrong sums, never stray accesses.
-// PL: the leaves are precomputed products, prod[bpos[k - row_ptr[0]]] (the
-// banded family), instead of val[k] * x[col[k]].
-template <int B, bool PL>
+template <int B>
 __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col,
                                                   const double* __restrict__ val,
@@ -380,8 +375,7 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
                                                   const int32_t* __restrict__ sunit,
                                                   const int32_t* __restrict__ unit_ptr,
                                                   double* __restrict__ unit_sums, int64_t units,
-                                                  SpmvEpi ep, const double* __restrict__ prod,
-                                                  const int32_t* __restrict__ bpos) {
+                                                  SpmvEpi ep) {
     constexpr int D = 4 * B;
     // a unit that starts just below the block's cost limit may extend 64
     // leaves past it: at most D + 64 leaves and D rows per block
@@ -404,14 +398,7 @@ __global__ __launch_bounds__(B) void k_merge_path(int n, const int32_t* __restri
         const int p = (int)threadIdx.x + e * B;
         if (p < cnt) {
             const int64_t k = (int64_t)e0 + p;
-            if constexpr (PL) {
-                const int64_t q = k - kbeg;
-                s[p] = (k >= kbeg && k < kend) ? prod[min(max((int64_t)bpos[q], (int64_t)0),
-                                                          (int64_t)(kend - kbeg) - 1)]
-                                               : 0.0;
-            } else {
-                s[p] = (k >= kbeg && k < kend) ? val[k] * x[col[k]] : 0.0;
-            }
+            s[p] = (k >= kbeg && k < kend) ? val[k] * x[col[k]] : 0.0;
         }
     }
     __syncthreads();
@@ -548,8 +535,7 @@ hipError_t spmv_prepare_merge(SpmvPlan& p, int B, hipStream_t s) {
 }
 
 hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col, const double* val,
-                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep,
-                           const double* prod, const int32_t* bpos) {
+                           const double* x, double* y, hipStream_t s, const SpmvEpi& ep) {
     const int B = v.bx;
     const SpmvPlan::MergeSplit* m = nullptr;
     for (const auto& q : p.mp)
@@ -558,14 +544,9 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
     switch (B) {
 #define AO_MP(BB)                                                                            \
     case BB:                                                                                 \
-        if (prod)                                                                            \
-            hipLaunchKernelGGL((k_merge_path<BB, true>), dim3(m->blocks), dim3(BB), 0, s, p.n, \
-                               p.row_ptr, col, val, x, y, m->srow, m->sunit, p.unit_ptr,     \
-                               p.unit_sums, p.units, ep, prod, bpos);                        \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_merge_path<BB, false>), dim3(m->blocks), dim3(BB), 0, s,   \
-                               p.n, p.row_ptr, col, val, x, y, m->srow, m->sunit,            \
-                               p.unit_ptr, p.unit_sums, p.units, ep, nullptr, nullptr);      \
+        hipLaunchKernelGGL((k_merge_path<BB>), dim3(m->blocks), dim3(BB), 0, s, p.n,          \
+                           p.row_ptr, col, val, x, y, m->srow, m->sunit, p.unit_ptr,          \
+                           p.unit_sums, p.units, ep);                                         \
         break;
         AO_MP(64) AO_MP(128) AO_MP(256) AO_MP(512) AO_MP(1024)
 #undef AO_MP
@@ -580,255 +561,6 @@ hipError_t spmv_merge_path(const ao_variant& v, SpmvPlan& p, const int32_t* col,
     return hipGetLastError();
 }
 
-
-// ---- banded: L2-resident slices of x ----------------------------------------
-//
-// Column c belongs to band min(c / W, nb - 1), W = ceil(n / nb).  The plan
-// gives every CSR entry k a place in a band-major copy (band outer, then
-// row, then storage order inside the row).  Per execution: the values are
-// copied to their places, products are formed band by band -- workgroup g
-// runs on XCD g % 8 (round-robin dispatch), and XCD x takes bands x, x+8,
-// ..., so the x slice an XCD gathers from stays in its L2 -- and the rows
-// are summed by merge-path with the products as leaves, in the canonical
-// order (a row's leaves are read back in storage order).
-
-namespace {
-
-constexpr int kBandChunk = 2048;  // products per workgroup (256 threads x 8)
-
-__device__ __forceinline__ int band_of(int32_t c, int64_t W, int nb) {
-    const int64_t b = (int64_t)c / W;
-    return (int)(b < 0 ? 0 : (b >= nb ? nb - 1 : b));
-}
-
-// cnt[b*n + i] = entries of row i in band b (thread per row)
-__global__ __launch_bounds__(256) void k_band_count(int n, const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, int nb,
-                                                    int64_t W, int32_t* __restrict__ cnt) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
-    const int32_t kb = row_ptr[i], ke = row_ptr[i + 1];
-    for (int b = 0; b < nb; ++b) {
-        int32_t c = 0;
-        for (int32_t k = kb; k < ke; ++k) c += band_of(col[k], W, nb) == b;
-        cnt[(int64_t)b * n + i] = c;
-    }
-}
-
-// exclusive scan of cnt (count entries, 1024 per block) -> out, block sums
-__global__ __launch_bounds__(1024) void k_scan_block(int64_t count, const int32_t* __restrict__ in,
-                                                     int32_t* __restrict__ out,
-                                                     int32_t* __restrict__ block_sums) {
-    __shared__ int32_t sh[1024];
-    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    const int32_t v = i < count ? in[i] : 0;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele
-        const int32_t t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += t;
-        __syncthreads();
-    }
-    if (i < count) out[i] = sh[threadIdx.x] - v;
-    if (threadIdx.x == 1023) block_sums[blockIdx.x] = sh[1023];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_add(int64_t count, int32_t* __restrict__ out,
-                                                   const int32_t* __restrict__ block_sums,
-                                                   const int32_t* __restrict__ total) {
-    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-    if (i < count) out[i] += block_sums[blockIdx.x];
-    if (i == 0) out[count] = *total;
-}
-
-// places: bpos[k - kbeg] and bcol[place] (thread per row)
-__global__ __launch_bounds__(256) void k_band_place(int n, const int32_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, int nb,
-                                                    int64_t W, const int32_t* __restrict__ bstart,
-                                                    int64_t places, int32_t* __restrict__ bcol,
-                                                    int32_t* __restrict__ bpos) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
-    const int32_t kbeg = row_ptr[0];
-    const int32_t kb = row_ptr[i], ke = row_ptr[i + 1];
-    for (int b = 0; b < nb; ++b) {
-        int32_t pos = bstart[(int64_t)b * n + i];
-        for (int32_t k = kb; k < ke; ++k) {
-            const int32_t c = col[k];
-            if (band_of(c, W, nb) != b) continue;
-            const int64_t q = (int64_t)k - kbeg;
-            if (q >= 0 && q < places && pos >= 0 && pos < places) {
-                bpos[q] = pos;
-                bcol[pos] = c;
-            }
-            ++pos;
-        }
-    }
-}
-
-// bval[bpos[q]] = val[kbeg + q]
-__global__ __launch_bounds__(256) void k_band_permute(int64_t places, int32_t kbeg,
-                                                      const double* __restrict__ val,
-                                                      const int32_t* __restrict__ bpos,
-                                                      double* __restrict__ bval) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= places) return;
-    const int32_t pos = bpos[q];
-    if (pos >= 0 && pos < places) bval[pos] = val[kbeg + q];
-}
-
-struct BandOff {
-    int64_t o[33];
-};
-
-// prod[j] = bval[j] * x[bcol[j]] over the band-major places, band by band
-// per XCD (see above); streaming operands bypass the caches so that the x
-// slice stays in L2
-__global__ __launch_bounds__(256) void k_band_products(const int32_t* __restrict__ bcol,
-                                                       const double* __restrict__ bval,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ prod, BandOff off,
-                                                       int nb, int chunks) {
-    const int g = (int)blockIdx.x;
-    const int xcd = g & 7, local = g >> 3;
-    const int band = xcd + 8 * (local / chunks);
-    const int chunk = local % chunks;
-    if (band >= nb) return;
-    const int64_t lo = off.o[band] + (int64_t)chunk * kBandChunk;
-    const int64_t hi = min(off.o[band + 1], lo + kBandChunk);
-    // all loads of the thread's 8 places first, then the 8 gathers, then the
-    // stores, so that the gathers overlap
-    constexpr int U = kBandChunk / 256;
-    int32_t c[U];
-    double v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = lo + threadIdx.x + 256 * u;
-        c[u] = j < hi ? __builtin_nontemporal_load(bcol + j) : 0;
-        v[u] = j < hi ? __builtin_nontemporal_load(bval + j) : 0.0;
-    }
-    double xg[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = lo + threadIdx.x + 256 * u;
-        xg[u] = j < hi ? x[c[u]] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = lo + threadIdx.x + 256 * u;
-        if (j < hi) __builtin_nontemporal_store(v[u] * xg[u], prod + j);
-    }
-}
-
-}  // namespace
-
-hipError_t spmv_prepare_banded(SpmvPlan& p, int nb, const int32_t* col, hipStream_t s) {
-    for (const auto& b : p.bands)
-        if (b.nb == nb) return hipSuccess;
-    if (nb < 8 || nb > 32 || nb % 8 != 0) return hipErrorInvalidConfiguration;
-    if (p.n <= 0) {
-        SpmvPlan::Banding b;
-        b.nb = nb;
-        b.off.assign(nb + 1, 0);
-        p.bands.push_back(b);
-        return hipSuccess;
-    }
-    const int64_t n = p.n, W = (n + nb - 1) / nb;
-    const int64_t count = (int64_t)nb * n;
-    const int64_t blocks = (count + 1023) / 1024;
-    SpmvPlan::Banding b;
-    b.nb = nb;
-    int32_t* cnt = nullptr;
-    int32_t* bs = nullptr;
-    hipError_t e = hipMalloc(&b.bstart, (size_t)(count + 1) * 4);
-    if (e == hipSuccess) e = hipMalloc(&cnt, (size_t)count * 4);
-    if (e == hipSuccess) e = hipMalloc(&bs, (size_t)(blocks + 1) * 4);
-    auto cleanup = [&]() {
-        if (cnt) hipFree(cnt);
-        if (bs) hipFree(bs);
-        if (b.bstart) hipFree(b.bstart);
-        if (b.bcol) hipFree(b.bcol);
-        if (b.bpos) hipFree(b.bpos);
-    };
-    if (e != hipSuccess) {
-        cleanup();
-        return e;
-    }
-    const unsigned rgrid = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_band_count, dim3(rgrid), dim3(256), 0, s, p.n, p.row_ptr, col, nb, W, cnt);
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)blocks), dim3(1024), 0, s, count, cnt, b.bstart,
-                       bs);
-    hipLaunchKernelGGL(k_units_top, dim3(1), dim3(1024), 0, s, (int)blocks, bs, bs + blocks);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)blocks), dim3(1024), 0, s, count, b.bstart, bs,
-                       bs + blocks);
-    e = hipGetLastError();
-    // band offsets: bstart[b*n] for b = 0..nb (the last is the total), and
-    // the CSR offset of the first entry
-    std::vector<int32_t> offs(nb + 1);
-    for (int q = 0; q <= nb && e == hipSuccess; ++q)
-        e = hipMemcpyAsync(&offs[q], b.bstart + (int64_t)q * n, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&b.kbeg, p.row_ptr, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        cleanup();
-        return e;
-    }
-    const int64_t places = offs[nb];
-    b.off.assign(offs.begin(), offs.end());
-    int64_t largest = 0;
-    for (int q = 0; q < nb; ++q) largest = std::max(largest, b.off[q + 1] - b.off[q]);
-    b.chunks = (int)std::max<int64_t>(1, (largest + kBandChunk - 1) / kBandChunk);
-    if ((int64_t)nb * b.chunks > 0x7fffffff) {
-        cleanup();
-        return hipErrorInvalidConfiguration;
-    }
-    e = hipMalloc(&b.bcol, (size_t)std::max<int64_t>(places, 1) * 4);
-    if (e == hipSuccess) e = hipMalloc(&b.bpos, (size_t)std::max<int64_t>(places, 1) * 4);
-    if (e == hipSuccess && !p.bval) e = hipMalloc(&p.bval, (size_t)std::max<int64_t>(places, 1) * 8);
-    if (e == hipSuccess && !p.prod) e = hipMalloc(&p.prod, (size_t)std::max<int64_t>(places, 1) * 8);
-    if (e != hipSuccess) {
-        cleanup();
-        return e;
-    }
-    hipLaunchKernelGGL(k_band_place, dim3(rgrid), dim3(256), 0, s, p.n, p.row_ptr, col, nb, W,
-                       b.bstart, places, b.bcol, b.bpos);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(cnt);
-    hipFree(bs);
-    cnt = bs = nullptr;
-    if (e != hipSuccess) {
-        cleanup();
-        return e;
-    }
-    p.bands.push_back(b);
-    return hipSuccess;
-}
-
-hipError_t spmv_banded(const ao_variant& v, SpmvPlan& p, const double* val, const double* x,
-                       double* y, hipStream_t s, const SpmvEpi& ep, bool values_ready) {
-    const int nb = v.by == 0 ? 16 : v.by;
-    const SpmvPlan::Banding* b = nullptr;
-    for (const auto& q : p.bands)
-        if (q.nb == nb) b = &q;
-    if (!b) return hipErrorNotReady;  // plan not prepared (the runtime prepares it)
-    const int64_t places = b->off.empty() ? 0 : b->off[nb];
-    if (places > 0) {
-        if (!values_ready)
-            hipLaunchKernelGGL(k_band_permute, dim3((unsigned)((places + 255) / 256)), dim3(256), 0,
-                               s, places, b->kbeg, val, b->bpos, p.bval);
-        BandOff off{};
-        for (int q = 0; q <= nb; ++q) off.o[q] = b->off[q];
-        hipLaunchKernelGGL(k_band_products, dim3((unsigned)(nb * b->chunks)), dim3(256), 0, s,
-                           b->bcol, p.bval, x, p.prod, off, nb, b->chunks);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    ao_variant mv = v;
-    mv.family = AO_FAM_SPMV_MERGE_PATH;
-    return spmv_merge_path(mv, p, nullptr, nullptr, x, y, s, ep, p.prod, b->bpos);
-}
 
 // ---- gather probe ------------------------------------------------------------
 //

@@ -5,7 +5,7 @@ from __future__ import annotations
 
 from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_NT_STORE, AO_VF_STAGED,
                    FAM_JACOBI_DIRECT, FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T3,
-                   FAM_JACOBI_ZREG_T4, FAM_SPMV_BANDED,
+                   FAM_JACOBI_ZREG_T4, FAM_SPMV_XSLICE,
                    FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, Variant)
 
 
@@ -37,14 +37,14 @@ def jacobi_variants_sweep():
     return out
 
 
-def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64, banded=()):
+def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64, xslice=()):
     """{thread-per-row, wavefront-per-row, merge-path} x block sizes, then the
-    banded family for each (merge-path block size, bands) in `banded`."""
+    x-slice family for each log2 slice width (13 or 14) in `xslice`."""
     out = []
     for fam in (FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, FAM_SPMV_MERGE_PATH):
         for b in blocks:
             out.append(Variant(AO_TARGET_GPU, fam, b, wave_lanes if fam == FAM_SPMV_WAVE_ROW else 0,
                                1, 0))
-    for b, nb in banded:
-        out.append(Variant(AO_TARGET_GPU, FAM_SPMV_BANDED, b, nb, 1, 0))
+    for swl in xslice:
+        out.append(Variant(AO_TARGET_GPU, FAM_SPMV_XSLICE, 0, swl, 1, 0))
     return out

@@ -24,8 +24,8 @@ def env():
 def _variants(ao):
     vs = ao.spmv_variants(blocks=(64, 256, 1024))
     vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, 128, 0, 1, 0))
-    vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_BANDED, 1024, 16, 1, 0))
-    vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_BANDED, 128, 8, 1, 0))
+    vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, 14, 1, 0))
+    vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, 13, 1, 0))
     return vs
 
 
@@ -104,5 +104,5 @@ def test_full_size_2_22(env, orc):
     vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_THREAD_ROW, 256, 0, 1, 0),
           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_WAVE_ROW, 256, 0, 1, 0),
           ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, 1024, 0, 1, 0),
-          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_BANDED, 1024, 16, 1, 0)]
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, 14, 1, 0)]
     _check_all(ao, torch, dev, st, orc, m, [(2.0 / 3.0, 2)], "gpu_relax_full", variants=vs)

@@ -29,8 +29,8 @@ def _variants(ao):
         vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_WAVE_ROW, 256, w, 1, 0))
     for b in (128, 512):
         vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, b, 0, 1, 0))
-    for b, nb in ((256, 8), (1024, 16), (64, 32), (512, 0)):
-        vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_BANDED, b, nb, 1, 0))
+    for swl in (13, 14, 0):
+        vs.append(ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, swl, 1, 0))
     return vs
 
 
@@ -142,10 +142,11 @@ def test_full_size_2_22(env, orc):
     n = 1 << 22
     t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
     y = torch.empty(n, dtype=torch.float64, device=dev)
-    h = ao.region_declare_variants("full22", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
-                                   model_type="roundrobin")
-    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
-    for v in range(9):
+    vs = ao.spmv_variants(xslice=(13, 14))
+    h = ao.region_declare_variants("full22", ao.AO_CSR_SPMV_F64, vs, model_type="roundrobin")
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size),
+                     values_id=1)
+    for v in list(range(len(vs))) + [9, 10]:  # the x-slice ones again: reordered values reused
         y.fill_(float("nan"))
         ao.region_run(h, a, stream=st, variant=v)
         torch.cuda.synchronize()
@@ -165,14 +166,15 @@ def test_reused_buffers_same_n_and_nnz(env, orc):
     assert ma["col"].size == mb["col"].size and not np.array_equal(ma["row_ptr"], mb["row_ptr"])
     t = {k: torch.from_numpy(v).to(dev) for k, v in ma.items()}
     y = torch.empty(n, dtype=torch.float64, device=dev)
-    h = ao.region_declare_variants("reuse", ao.AO_CSR_SPMV_F64, ao.spmv_variants(),
-                                   model_type="roundrobin")
-    for m in (ma, mb):
+    vs = ao.spmv_variants(xslice=(13, 14))
+    h = ao.region_declare_variants("reuse", ao.AO_CSR_SPMV_F64, vs, model_type="roundrobin")
+    for q, m in enumerate((ma, mb)):
         for k, v in m.items():
             t[k].copy_(torch.from_numpy(v))
-        a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size))
+        a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n, int(m["col"].size),
+                         values_id=q + 1)
         want = orc.spmv_canonical(m["row_ptr"], m["col"], m["val"], m["x"])
-        for v in range(9):
+        for v in range(len(vs)):
             y.fill_(float("nan"))
             ao.region_run(h, a, stream=st, variant=v)
             torch.cuda.synchronize()
@@ -200,3 +202,64 @@ def test_gather_probe_sums(env):
         g, t = divmod(k, 2048)
         want[4 * g + (t % 256) // 64] += x[ic[k]]
     assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+def test_xslice_values_id(env, orc):
+    # The x-slice family keeps the values in its own order: with values id 0
+    # the copy is refreshed every call; a nonzero id lets calls reuse it, and
+    # changed values under a new id are picked up
+    ao, torch, dev, st = env
+    n = 20000
+    m = synth.csr_matrix(n, 91, mean=16.0, max_len=2000)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in m.items()}
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    h = ao.region_declare_variants("xs_values", ao.AO_CSR_SPMV_F64,
+                                   [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, 13, 1, 0)],
+                                   model_type="roundrobin")
+    sid = 424242
+
+    def run(vid):
+        y.fill_(float("nan"))
+        ao.region_run(h, ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, n,
+                                      int(m["col"].size), structure_id=sid, values_id=vid),
+                      stream=st, variant=0)
+        torch.cuda.synchronize()
+        return y.cpu().numpy()
+
+    want = orc.spmv_canonical(m["row_ptr"], m["col"], m["val"], m["x"])
+    assert np.array_equal(run(5), want)
+    assert np.array_equal(run(5), want)        # reordered values reused
+    val2 = m["val"] * -0.5
+    t["val"].copy_(torch.from_numpy(val2))
+    want2 = orc.spmv_canonical(m["row_ptr"], m["col"], val2, m["x"])
+    assert np.array_equal(run(6), want2)       # new id: values reordered again
+    assert np.array_equal(run(0), want2)       # id 0: reordered on every call
+    t["val"].copy_(torch.from_numpy(m["val"]))
+    assert np.array_equal(run(0), want)
+    ao.region_destroy(h)
+
+
+def test_xslice_refuses_rows_above_its_limit(env, orc):
+    # a row of 5000 nonzeros is above the family's 4097 limit: its variant
+    # fails to launch and is masked, the others still run
+    ao, torch, dev, st = env
+    lens = np.full(300, 3, dtype=np.int64)
+    lens[17] = 5000
+    n = 8000
+    rp, col = synth.csr_structure(lens.size, n, lens, 95)
+    val = synth.normal_values(col.size, 95)
+    x = synth.dense_vector_pm1(n, 95)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in
+         {"row_ptr": rp, "col": col, "val": val, "x": x}.items()}
+    y = torch.empty(lens.size, dtype=torch.float64, device=dev)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_XSLICE, 0, 14, 1, 0),
+          ao.Variant(ao.AO_TARGET_GPU, ao.FAM_SPMV_MERGE_PATH, 256, 0, 1, 0)]
+    h = ao.region_declare_variants("xs_limit", ao.AO_CSR_SPMV_F64, vs, model_type="roundrobin")
+    a = ao.spmv_args(t["row_ptr"], t["col"], t["val"], t["x"], y, lens.size, int(col.size))
+    with pytest.raises(ao.AdaptError) as ei:
+        ao.region_run(h, a, stream=st, variant=0)
+    assert ei.value.code == -7 or "cannot launch" in str(ei.value)
+    ao.region_run(h, a, stream=st, variant=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), orc.spmv_canonical(rp, col, val, x))
+    ao.region_destroy(h)

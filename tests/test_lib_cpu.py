@@ -278,16 +278,15 @@ def test_relax_argument_errors(ao):
                                    [ao.jacobi_variants_sweep()[5]])
 
 
-def test_banded_spmv_variant_validation(ao):
+def test_xslice_spmv_variant_validation(ao):
     G = ao.AO_TARGET_GPU
-    ok = [ao.Variant(G, ao.FAM_SPMV_BANDED, b, nb, 1, 0) for b, nb in
-          ((64, 0), (256, 8), (1024, 16), (512, 32))]
+    ok = [ao.Variant(G, ao.FAM_SPMV_XSLICE, 0, swl, 1, 0) for swl in (0, 13, 14)]
     for kind in (ao.AO_CSR_SPMV_F64, ao.AO_CSR_RELAX_F64):
-        ao.region_destroy(ao.region_declare_variants(f"banded_ok_{kind}", kind, ok))
-    for b, nb in ((96, 16), (256, 12), (256, 64), (2048, 8)):
+        ao.region_destroy(ao.region_declare_variants(f"xslice_ok_{kind}", kind, ok))
+    for b, swl in ((256, 14), (0, 12), (0, 15), (0, 16)):
         with pytest.raises(ao.AdaptError):
-            ao.region_declare_variants(f"banded_bad_{b}_{nb}", ao.AO_CSR_SPMV_F64,
-                                       [ao.Variant(G, ao.FAM_SPMV_BANDED, b, nb, 1, 0)])
+            ao.region_declare_variants(f"xslice_bad_{b}_{swl}", ao.AO_CSR_SPMV_F64,
+                                       [ao.Variant(G, ao.FAM_SPMV_XSLICE, b, swl, 1, 0)])
 
 
 @pytest.mark.parametrize("resident", [0, 1])
