@@ -279,10 +279,13 @@ def batch_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
     print(json.dumps(batch_measure(steps, warmup, no_cpu_baseline)), flush=True)
 
 
-def batch_pmc_traffic():
+def batch_pmc_traffic(chosen):
     """HBM bytes per graph replay of the batched launch from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE over the graph's passes,
-    scaled by the copy-probe calibration), when one was taken."""
+    scaled by the copy-probe calibration), when it was taken with these
+    kernel sources and the same tiles on the three largest size buckets
+    (maximum dimension above 32: all but a fraction of a percent of the
+    points)."""
     path = os.path.join(ROOT, "profiles", "batch_graph_pmc.json")
     try:
         with open(path) as fh:
@@ -290,6 +293,8 @@ def batch_pmc_traffic():
     except (OSError, ValueError):
         return None
     if d.get("source_sha256") != source_digest(BATCH_SOURCES):
+        return None
+    if list(d.get("autotuned_candidates", []))[2:] != list(chosen)[2:]:
         return None
     return d.get("traffic_bytes_per_replay")
 
@@ -410,7 +415,7 @@ def batch_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
     min_bytes = ao.batch_min_traffic(b)
     ao.batch_destroy(b)
     achieved = min_bytes / t_graph[0] / 1e9
-    traffic = batch_pmc_traffic()
+    traffic = batch_pmc_traffic(chosen)
     res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": traffic,

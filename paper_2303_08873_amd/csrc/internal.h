@@ -70,11 +70,16 @@ struct SpmvPlan {
         int32_t* rb = nullptr;          // [nb + 1] first row of each block
         int32_t* off = nullptr;         // [ns*nb + 1] first place of piece (slice s, block t) at s*nb+t
         int32_t* unit_ptr = nullptr;    // [n + 1] first 64-leaf unit of each row
-        int32_t* chunk_first = nullptr; // [ns + 1] first products chunk of each slice
+        int4* chunk_table = nullptr;    // [chunks] (slice, first place, end place, 0) per products workgroup
         int chunks = 0;
         uint16_t* bcol = nullptr;       // [places] column inside the slice
-        uint16_t* bk = nullptr;         // [places] nonzero index inside the row block
-        uint32_t* uinfo = nullptr;      // [units] row inside its block << 16 | unit index in the row
+        int32_t* ej = nullptr;          // [places] per element (a block's places in place order,
+                                        // blocks in row order): its place
+        uint16_t* bke = nullptr;        // [places] per element: its nonzero's index inside the block
+        uint64_t* uinfo = nullptr;      // [units] unit descriptors (first nonzero and count, the
+                                        // row's unit count, row inside the block, index in the row)
+        int32_t* ub = nullptr;          // [nb + 1] first unit of each block
+        int32_t* kbt = nullptr;         // [nb + 1] first nonzero of each block
         double* bval = nullptr;         // [places] values in place order
         double* prod = nullptr;         // [places] products in place order
         int64_t units = 0, places = 0;

@@ -30,9 +30,12 @@ namespace {
 constexpr int kDN = 4096;      // cost units (nonzeros + rows) per row block
 constexpr int kDCAP = 8192;    // nonzeros a row block can hold in LDS
 constexpr int kMaxSlices = 1024;
-constexpr int kRedThreads = 512;
+constexpr int kRedThreads = 1024;
 constexpr int kProdThreads = 1024;
-constexpr int kProdChunk = 65536;  // places per products workgroup
+constexpr int kProdChunk = 65536;  // places per products workgroup (target)
+
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ---- plan ----------------------------------------------------------------
 
@@ -143,21 +146,53 @@ __global__ __launch_bounds__(1024) void k_xs_scan_add(int64_t count, int32_t* __
     if (i == 0) out[count] = *total;
 }
 
+// first place of each slice: starts[s] = off[s * nb]
+__global__ __launch_bounds__(256) void k_xs_slice_starts(int nb, int ns,
+                                                         const int32_t* __restrict__ off,
+                                                         int32_t* __restrict__ starts) {
+    const int q = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (q < ns) starts[q] = off[(int64_t)q * nb];
+}
+
 // Places (one wave per block): the block's nonzeros in CSR order, 64 at a
 // time; a lane's place is its slice's cursor plus the number of earlier
 // lanes of the chunk in the same slice, so each piece keeps CSR order.
+// The block's elements are its places in place order (its pieces one
+// after the other): element e of block t sits at index kbt[t] - k0 + e of
+// the element arrays, which hold its place (ej) and its nonzero's index
+// inside the block (bke, the LDS slot it is summed in).
 __global__ __launch_bounds__(64) void k_xs_place(int nb, int ns, int sw,
                                                  const int32_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ col,
                                                  const int32_t* __restrict__ rb,
                                                  const int32_t* __restrict__ off, int64_t places,
                                                  uint16_t* __restrict__ bcol,
-                                                 uint16_t* __restrict__ bk) {
+                                                 int32_t* __restrict__ ej,
+                                                 uint16_t* __restrict__ bke) {
     __shared__ int32_t cur[kMaxSlices];
+    __shared__ int32_t ebase[kMaxSlices];  // element index of each piece's first place
     const int t = (int)blockIdx.x;
     const int lane = (int)threadIdx.x;
-    for (int s = lane; s < ns; s += 64) cur[s] = off[(int64_t)s * nb + t];
+    int32_t carry = 0;
+    for (int base = 0; base < ns; base += 64) {
+        const int s = base + lane;
+        int32_t len = 0;
+        if (s < ns) {
+            const int64_t q = (int64_t)s * nb + t;
+            cur[s] = off[q];
+            len = off[q + 1] - off[q];
+        }
+        int32_t v = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t w = __shfl_up(v, d);
+            if (lane >= d) v += w;
+        }
+        if (s < ns) ebase[s] = carry + v - len;
+        carry += __shfl(v, 63);
+    }
     __syncthreads();
+    const int32_t k0 = row_ptr[0];
     const int32_t kb = row_ptr[rb[t]], ke = row_ptr[rb[t + 1]];
     for (int32_t c = kb; c < ke; c += 64) {
         const int32_t k = c + lane;
@@ -171,14 +206,21 @@ __global__ __launch_bounds__(64) void k_xs_place(int nb, int ns, int sw,
             same += eq;
             before += (m < lane) ? eq : 0;
         }
-        int32_t base = 0;
-        if (live) base = cur[s];
+        int32_t base = 0, eb = 0, st = 0;
+        if (live) {
+            base = cur[s];
+            eb = ebase[s];
+            st = off[(int64_t)s * nb + t];
+        }
         __syncthreads();
         if (live) {
             const int64_t j = (int64_t)base + before;
-            if (j >= 0 && j < places) {
-                bcol[j] = (uint16_t)(cc - (s << sw));
-                bk[j] = (uint16_t)(k - kb);
+            const int64_t e = (int64_t)eb + (j - st);   // element index inside the block
+            const int64_t x = (int64_t)(kb - k0) + e;   // its slot in the element arrays
+            if (j >= 0 && j < places) bcol[j] = (uint16_t)(cc - (s << sw));
+            if (x >= 0 && x < places) {
+                ej[x] = (int32_t)j;
+                bke[x] = (uint16_t)(k - kb);
             }
             if (before == same - 1) cur[s] = base + same;  // the slice's last lane
         }
@@ -195,63 +237,48 @@ __global__ __launch_bounds__(1024) void k_xs_unit_counts(int n, const int32_t* _
     nu[i] = len > 0 ? (len + 63) / 64 : 1;
 }
 
-// uinfo[u] = (row - rb[t]) << 16 | unit index in the row, for the units of
-// row i (its block t = cost(i) / DN)
+// Unit descriptors, 64 bits each, for the units of row i (its block t =
+// cost(i) / DN): bits 0-15 the unit's first nonzero inside the block, 16-23
+// its nonzero count (0..64), 24-31 the row's unit count, 32-47 the row
+// inside the block, 48-63 the unit's index in the row.
+__device__ __forceinline__ uint64_t unit_desc(int a, int m, int nu, int r, int jn) {
+    return (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)m << 16) | ((uint64_t)(uint32_t)nu << 24) |
+           ((uint64_t)(uint32_t)r << 32) | ((uint64_t)(uint32_t)jn << 48);
+}
+
 __global__ __launch_bounds__(256) void k_xs_units(int n, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ unit_ptr,
                                                   const int32_t* __restrict__ rb,
-                                                  int64_t units, uint32_t* __restrict__ uinfo) {
+                                                  int64_t units, uint64_t* __restrict__ uinfo) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
     const int t = (int)(((int64_t)(row_ptr[i] - row_ptr[0]) + i) / kDN);
-    const uint32_t r = (uint32_t)(i - rb[t]);
-    const int32_t u0 = unit_ptr[i], u1 = unit_ptr[i + 1];
-    for (int32_t u = u0; u < u1; ++u)
-        if (u >= 0 && u < units) uinfo[u] = (r << 16) | (uint32_t)(u - u0);
+    const int r = i - rb[t];
+    const int32_t rs = row_ptr[i] - row_ptr[rb[t]];
+    const int32_t len = row_ptr[i + 1] - row_ptr[i];
+    const int nu = len > 0 ? (len + 63) / 64 : 1;
+    const int32_t u0 = unit_ptr[i];
+    for (int jn = 0; jn < nu; ++jn) {
+        const int64_t u = (int64_t)u0 + jn;
+        const int m = min(max(len - 64 * jn, 0), 64);
+        if (u >= 0 && u < units) uinfo[u] = unit_desc(rs + 64 * jn, m, nu, r, jn);
+    }
+}
+
+// per block t: first unit ub[t] = unit_ptr[rb[t]], first nonzero kbt[t] =
+// row_ptr[rb[t]] (t = 0..nb)
+__global__ __launch_bounds__(256) void k_xs_block_info(int nb, const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ rb,
+                                                       const int32_t* __restrict__ unit_ptr,
+                                                       int32_t* __restrict__ ub,
+                                                       int32_t* __restrict__ kbt) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t > nb) return;
+    ub[t] = unit_ptr[rb[t]];
+    kbt[t] = row_ptr[rb[t]];
 }
 
 // ---- execution -----------------------------------------------------------
-
-// The pieces of block t: starts (slice-major offsets) and an inclusive
-// prefix of their lengths, in LDS; returns the block's place count.
-__device__ int load_pieces(int t, int ns, int nb, const int32_t* __restrict__ off, int32_t* start,
-                           int32_t* pre) {
-    // piece (s, t) = [off[s*nb + t], off[s*nb + t + 1])
-    for (int s = (int)threadIdx.x; s < ns; s += (int)blockDim.x) {
-        const int64_t q = (int64_t)s * nb + t;
-        start[s] = off[q];
-        pre[s] = off[q + 1] - off[q];
-    }
-    __syncthreads();
-    // inclusive scan of pre[0..ns) by one wave (ns <= kMaxSlices)
-    if (threadIdx.x < 64) {
-        int32_t carry = 0;
-        for (int base = 0; base < ns; base += 64) {
-            const int s = base + (int)threadIdx.x;
-            int32_t v = s < ns ? pre[s] : 0;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int32_t a = __shfl_up(v, d);
-                if ((int)threadIdx.x >= d) v += a;
-            }
-            if (s < ns) pre[s] = carry + v;
-            carry += __shfl(v, 63);
-        }
-    }
-    __syncthreads();
-    return ns > 0 ? pre[ns - 1] : 0;
-}
-
-// place of the e-th entry of the block (pieces in slice order)
-__device__ __forceinline__ int64_t place_of(int e, int ns, const int32_t* start, const int32_t* pre) {
-    int lo = 0, hi = ns - 1;  // first s with pre[s] > e
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] > e) hi = mid; else lo = mid + 1;
-    }
-    const int32_t before = lo > 0 ? pre[lo - 1] : 0;
-    return (int64_t)start[lo] + (e - before);
-}
 
 // XCD-aware order: consecutive blocks on one XCD (round-robin dispatch puts
 // workgroup g on XCD g % 8), so the line shared by the pieces of adjacent
@@ -261,67 +288,95 @@ __device__ __forceinline__ int xcd_block(int g, int nb) {
     return (g & 7) * per + (g >> 3);
 }
 
-// bval[place] = val[kb + bk[place]] (workgroup per row block)
-__global__ __launch_bounds__(kRedThreads) void k_xs_permute(int nb, int ns, int64_t places,
-                                                            const int32_t* __restrict__ row_ptr,
-                                                            const int32_t* __restrict__ rb,
-                                                            const int32_t* __restrict__ off,
-                                                            const uint16_t* __restrict__ bk,
+// A row block holds at most DCAP elements; a thread of a kRedThreads-wide
+// workgroup takes elements e = thread + q * kRedThreads, q < kPer, and
+// issues all their loads together.
+constexpr int kPer = kDCAP / kRedThreads;
+
+// bval[ej[x]] = val[kb + bke[x]] over the elements x of each row block
+// (workgroup per row block)
+__global__ __launch_bounds__(kRedThreads) void k_xs_permute(int nb, int64_t places,
+                                                            const int32_t* __restrict__ kbt,
+                                                            const int32_t* __restrict__ ej,
+                                                            const uint16_t* __restrict__ bke,
                                                             const double* __restrict__ val,
                                                             double* __restrict__ bval) {
-    __shared__ int32_t start[kMaxSlices], pre[kMaxSlices];
     const int t = xcd_block((int)blockIdx.x, nb);
     if (t >= nb) return;
-    const int total = load_pieces(t, ns, nb, off, start, pre);
-    const int32_t kb = row_ptr[rb[t]], kend = row_ptr[rb[nb]];
-    for (int e = (int)threadIdx.x; e < total; e += kRedThreads) {
-        const int64_t j = min(max(place_of(e, ns, start, pre), (int64_t)0), places - 1);
-        bval[j] = val[min(kb + (int32_t)bk[j], kend - 1)];
+    const int32_t k0 = kbt[0], kb = kbt[t], kend = kbt[nb];
+    const int total = min(kbt[t + 1] - kb, kDCAP);
+    const int64_t x0 = (int64_t)(kb - k0);
+    int32_t j[kPer];
+    uint16_t b[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = (int)threadIdx.x + q * kRedThreads;
+        const bool live = e < total;
+        j[q] = live ? min(max(ej[x0 + e], 0), (int32_t)(places - 1)) : -1;
+        b[q] = live ? bke[x0 + e] : (uint16_t)0;
     }
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v[q] = j[q] >= 0 ? val[min(kb + (int32_t)b[q], kend - 1)] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+        if (j[q] >= 0) bval[j[q]] = v[q];
 }
 
-// prod[place] = bval[place] * x[slice base + bcol[place]] over one chunk of
-// one slice, x of the slice in LDS
+// prod[place] = bval[place] * x[slice base + bcol[place]] over one chunk
+// (a range of one slice's places), x of the slice in LDS.  Places go in
+// aligned groups of four (8-byte column and 32-byte value and product
+// accesses); groups cut by the chunk's ends take the elementwise path.
 template <int SWL>
-__global__ __launch_bounds__(kProdThreads) void k_xs_products(int64_t ncols, int ns, int nb,
-                                                              const int32_t* __restrict__ off,
-                                                              const int32_t* __restrict__ chunk_first,
+__global__ __launch_bounds__(kProdThreads) void k_xs_products(int64_t ncols,
+                                                              const int4* __restrict__ chunks,
                                                               const uint16_t* __restrict__ bcol,
                                                               const double* __restrict__ bval,
                                                               const double* __restrict__ x,
                                                               double* __restrict__ prod) {
     constexpr int SW = 1 << SWL;
     __shared__ double xs[SW];
-    // chunk g belongs to the slice s with chunk_first[s] <= g < chunk_first[s + 1]
-    const int g = (int)blockIdx.x;
-    int lo = 0, hi = ns - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (chunk_first[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    const int s = lo;
-    const int64_t base = (int64_t)s << SWL;
+    const int4 ch = chunks[blockIdx.x];  // slice, first place, end place, unused
+    const int64_t base = (int64_t)ch.x << SWL;
     const int w = (int)min((int64_t)SW, ncols - base);
     for (int c = (int)threadIdx.x; c < SW; c += kProdThreads) xs[c] = c < w ? x[base + c] : 0.0;
     __syncthreads();
-    const int64_t p0 = off[(int64_t)s * nb], p1 = off[(int64_t)(s + 1) * nb];
-    const int64_t lo_j = p0 + (int64_t)(g - chunk_first[s]) * kProdChunk;
-    const int64_t hi_j = min(p1, lo_j + kProdChunk);
-    constexpr int U = 4;
-    for (int64_t j0 = lo_j + threadIdx.x; j0 < hi_j; j0 += (int64_t)kProdThreads * U) {
-        uint16_t c[U];
-        double v[U];
+    const int64_t lo = ch.y, hi = ch.z;
+    const int64_t g0 = lo >> 2, g1 = (hi + 3) >> 2;
+    // interior groups (all four places inside the chunk) in batches of two
+    // per thread, loads first; the (at most two) cut groups elementwise
+    const int64_t a = (lo + 3) >> 2, b = hi >> 2;  // groups [a, b) lie inside
+    constexpr int G = 2;
+    for (int64_t g = a + threadIdx.x; g < b; g += (int64_t)kProdThreads * G) {
+        us4 c[G];
+        d2 v0[G], v1[G];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = j0 + (int64_t)u * kProdThreads;
-            c[u] = j < hi_j ? __builtin_nontemporal_load(bcol + j) : (uint16_t)0;
-            v[u] = j < hi_j ? __builtin_nontemporal_load(bval + j) : 0.0;
+        for (int u = 0; u < G; ++u) {
+            const int64_t gg = min(g + (int64_t)u * kProdThreads, b - 1);
+            c[u] = __builtin_nontemporal_load(reinterpret_cast<const us4*>(bcol) + gg);
+            v0[u] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(bval) + 2 * gg);
+            v1[u] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(bval) + 2 * gg + 1);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = j0 + (int64_t)u * kProdThreads;
-            if (j < hi_j) __builtin_nontemporal_store(v[u] * xs[c[u] & (SW - 1)], prod + j);
+        for (int u = 0; u < G; ++u) {
+            const int64_t gg = g + (int64_t)u * kProdThreads;
+            if (gg < b) {
+                d2 p0, p1;
+                p0.x = v0[u].x * xs[c[u].x & (SW - 1)];
+                p0.y = v0[u].y * xs[c[u].y & (SW - 1)];
+                p1.x = v1[u].x * xs[c[u].z & (SW - 1)];
+                p1.y = v1[u].y * xs[c[u].w & (SW - 1)];
+                __builtin_nontemporal_store(p0, reinterpret_cast<d2*>(prod) + 2 * gg);
+                __builtin_nontemporal_store(p1, reinterpret_cast<d2*>(prod) + 2 * gg + 1);
+            }
         }
+    }
+    if (threadIdx.x < 8) {
+        // the cut groups at the ends: g0 (if lo is not aligned) and b (if hi is not)
+        const int64_t g = threadIdx.x < 4 ? g0 : b;
+        const int64_t je = (g << 2) + (threadIdx.x & 3);
+        const bool cut = threadIdx.x < 4 ? (g0 < a) : (b < g1 && b >= a);
+        if (cut && je >= lo && je < hi) prod[je] = bval[je] * xs[bcol[je] & (SW - 1)];
     }
 }
 
@@ -380,53 +435,71 @@ __device__ __forceinline__ double out_value(const SpmvEpi& ep, const double* __r
     return x[i] + u;
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_xs_reduce(int n, int nb, int ns, int64_t places,
-                                                           const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(kRedThreads) void k_xs_reduce(int n, int nb, int64_t places,
                                                            const int32_t* __restrict__ rb,
-                                                           const int32_t* __restrict__ off,
-                                                           const uint16_t* __restrict__ bk,
+                                                           const int32_t* __restrict__ ub,
+                                                           const int32_t* __restrict__ kbt,
+                                                           const int32_t* __restrict__ ej,
+                                                           const uint16_t* __restrict__ bke,
                                                            const double* __restrict__ prod,
-                                                           const int32_t* __restrict__ unit_ptr,
-                                                           const uint32_t* __restrict__ uinfo,
+                                                           const uint64_t* __restrict__ uinfo,
                                                            const double* __restrict__ x,
                                                            double* __restrict__ y, SpmvEpi ep) {
     __shared__ double sl[kDCAP];
-    __shared__ int32_t start[kMaxSlices], pre[kMaxSlices];
     const int t = xcd_block((int)blockIdx.x, nb);
     if (t >= nb) return;
-    const int total = min(load_pieces(t, ns, nb, off, start, pre), kDCAP);
-    const int r0 = rb[t], r1 = rb[t + 1];
-    const int32_t kb = row_ptr[r0];
-    for (int e = (int)threadIdx.x; e < total; e += kRedThreads) {
-        const int64_t j = min(max(place_of(e, ns, start, pre), (int64_t)0), places - 1);
-        sl[bk[j] & (kDCAP - 1)] = prod[j];
+    // everything the block needs that does not depend on its products is
+    // requested up front: its elements, its first row and its units
+    const int r0 = rb[t];
+    const int32_t u0 = ub[t], u1 = ub[t + 1];
+    const int32_t k0 = kbt[0], kb = kbt[t];
+    const int total = min(kbt[t + 1] - kb, kDCAP);
+    const int64_t x0 = (int64_t)(kb - k0);
+    const int32_t uf = u0 + (int32_t)threadIdx.x;
+    const uint64_t first = uf < u1 ? uinfo[uf] : 0;
+    {
+        int32_t j[kPer];
+        uint16_t b[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = (int)threadIdx.x + q * kRedThreads;
+            const bool live = e < total;
+            j[q] = live ? min(max(ej[x0 + e], 0), (int32_t)(places - 1)) : -1;
+            b[q] = live ? bke[x0 + e] : (uint16_t)0;
+        }
+        double v[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) v[q] = j[q] >= 0 ? prod[j[q]] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (j[q] >= 0) sl[b[q] & (kDCAP - 1)] = v[q];
     }
     __syncthreads();
-    // one thread per unit: units of a row with one unit finish the row,
-    // others leave their sum in the unit's first leaf slot
-    const int32_t u0 = unit_ptr[r0], u1 = unit_ptr[r1];
-    for (int32_t u = u0 + (int32_t)threadIdx.x; u < u1; u += kRedThreads) {
-        const uint32_t info = uinfo[u];
-        const int i = min(r0 + (int)(info >> 16), r1 - 1);
-        const int jn = (int)(info & 0xffffu);
-        const int32_t rs = row_ptr[i] - kb, re = row_ptr[i + 1] - kb;
-        const int32_t a = rs + 64 * jn;
-        const int m = (int)min(max(re - a, 0), 64);
-        const bool in_lds = a >= 0 && a + m <= kDCAP;
+    // one thread per unit: a row of one unit is finished here; the units of
+    // longer rows leave their sum in their first nonzero's slot
+    for (int32_t u = uf; u < u1; u += kRedThreads) {
+        const uint64_t d = u == uf ? first : uinfo[u];
+        const int a = (int)(d & 0xffffu), m = (int)((d >> 16) & 0xffu);
+        const int nu = (int)((d >> 24) & 0xffu);
+        const int i = r0 + (int)((d >> 32) & 0xffffu);
+        const bool in_lds = a + m <= kDCAP;
         const double v = in_lds ? unit_sum(sl + a, m) : 0.0;
-        if (re - rs <= 64) {
-            if (i < n) y[i] = out_value(ep, x, i, re > rs ? v : 0.0);
+        if (nu <= 1) {
+            if (i < n) y[i] = out_value(ep, x, i, m > 0 ? v : 0.0);
         } else if (in_lds) {
             sl[a] = v;
         }
     }
     __syncthreads();
-    for (int i = r0 + (int)threadIdx.x; i < r1; i += kRedThreads) {
-        const int32_t rs = row_ptr[i] - kb, re = row_ptr[i + 1] - kb;
-        if (re - rs <= 64) continue;
-        const int nu = (re - rs + 63) / 64;
-        const bool in_lds = rs >= 0 && rs + 64 * (nu - 1) < kDCAP;
-        y[i] = out_value(ep, x, i, in_lds ? combine_units(sl + rs, nu) : 0.0);
+    // the first unit of each longer row combines the row's unit sums
+    for (int32_t u = uf; u < u1; u += kRedThreads) {
+        const uint64_t d = u == uf ? first : uinfo[u];
+        const int nu = (int)((d >> 24) & 0xffu), jn = (int)(d >> 48);
+        if (nu <= 1 || jn != 0) continue;
+        const int a = (int)(d & 0xffffu);
+        const int i = r0 + (int)((d >> 32) & 0xffffu);
+        const bool in_lds = a + 64 * (nu - 1) < kDCAP;
+        if (i < n) y[i] = out_value(ep, x, i, in_lds ? combine_units(sl + a, nu) : 0.0);
     }
 }
 
@@ -531,24 +604,60 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
     }
     q.units = units;
     q.places = places;
-    // chunks of the products pass: slice s takes ceil(places_s / chunk) of them
+    // the products pass is cut into chunks: each slice into equal ranges so
+    // that the whole pass is a whole number of rounds of the resident
+    // workgroups (one per 128 KB slice and CU, two per 64 KB slice)
     std::vector<int32_t> offs((size_t)ns + 1);
-    for (int64_t t = 0; t <= ns && e == hipSuccess; ++t)
-        e = hipMemcpyAsync(&offs[t], q.off + t * nb, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    std::vector<int32_t> first((size_t)ns + 1, 0);
-    for (int64_t t = 0; t < ns; ++t) {
-        const int64_t len = offs[t + 1] - offs[t];
-        first[t + 1] = first[t] + (int32_t)std::max<int64_t>(1, (len + kProdChunk - 1) / kProdChunk);
+    {
+        int32_t* starts = nullptr;
+        if (e == hipSuccess) e = hipMalloc(&starts, (size_t)ns * 4);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_xs_slice_starts, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0,
+                               s, (int)nb, (int)ns, q.off, starts);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(offs.data(), starts, (size_t)ns * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (starts) hipFree(starts);
     }
-    q.chunks = first[ns];
-    if (e == hipSuccess) e = hipMalloc(&q.chunk_first, ((size_t)ns + 1) * 4);
+    offs[ns] = places;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    const int64_t resident = (int64_t)cus * (swl == 13 ? 2 : 1);
+    const int64_t rounds =
+        std::max<int64_t>(1, (places + resident * kProdChunk / 2) / (resident * kProdChunk));
+    const double per = (double)std::max<int64_t>(places, 1) / (double)(rounds * resident);
+    std::vector<int4> chunks;
+    for (int64_t t = 0; t < ns; ++t) {
+        const int64_t lo = offs[t], hi = offs[t + 1];
+        const int64_t k = std::max<int64_t>(1, (int64_t)std::llround((double)(hi - lo) / per));
+        for (int64_t c = 0; c < k; ++c) {
+            int4 v;
+            v.x = (int)t;
+            v.y = (int)(lo + (hi - lo) * c / k);
+            v.z = (int)(lo + (hi - lo) * (c + 1) / k);
+            v.w = 0;
+            chunks.push_back(v);
+        }
+    }
+    q.chunks = (int)chunks.size();
+    if (e == hipSuccess) e = hipMalloc(&q.chunk_table, chunks.size() * sizeof(int4));
     if (e == hipSuccess)
-        e = hipMemcpy(q.chunk_first, first.data(), ((size_t)ns + 1) * 4, hipMemcpyHostToDevice);
+        e = hipMemcpy(q.chunk_table, chunks.data(), chunks.size() * sizeof(int4),
+                      hipMemcpyHostToDevice);
     const size_t pl = (size_t)std::max<int64_t>(places, 1);
     if (e == hipSuccess) e = hipMalloc(&q.bcol, pl * 2);
-    if (e == hipSuccess) e = hipMalloc(&q.bk, pl * 2);
-    if (e == hipSuccess) e = hipMalloc(&q.uinfo, (size_t)std::max<int64_t>(units, 1) * 4);
+    if (e == hipSuccess) e = hipMalloc(&q.ej, pl * 4);
+    if (e == hipSuccess) e = hipMalloc(&q.bke, pl * 2);
+    if (e == hipSuccess) e = hipMalloc(&q.uinfo, (size_t)std::max<int64_t>(units, 1) * 8);
+    if (e == hipSuccess) e = hipMalloc(&q.ub, (size_t)(nb + 1) * 4);
+    if (e == hipSuccess) e = hipMalloc(&q.kbt, (size_t)(nb + 1) * 4);
     if (e == hipSuccess) e = hipMalloc(&q.bval, pl * 8);
     if (e == hipSuccess) e = hipMalloc(&q.prod, pl * 8);
     if (e != hipSuccess) {
@@ -556,9 +665,11 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
         return e;
     }
     hipLaunchKernelGGL(k_xs_place, dim3((unsigned)nb), dim3(64), 0, s, (int)nb, (int)ns, swl,
-                       p.row_ptr, col, q.rb, q.off, (int64_t)places, q.bcol, q.bk);
+                       p.row_ptr, col, q.rb, q.off, (int64_t)places, q.bcol, q.ej, q.bke);
     hipLaunchKernelGGL(k_xs_units, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p.n,
                        p.row_ptr, q.unit_ptr, q.rb, (int64_t)units, q.uinfo);
+    hipLaunchKernelGGL(k_xs_block_info, dim3((unsigned)((nb + 256) / 256)), dim3(256), 0, s,
+                       (int)nb, p.row_ptr, q.rb, q.unit_ptr, q.ub, q.kbt);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     hipFree(cnt);
@@ -584,21 +695,20 @@ hipError_t spmv_xslice(const ao_variant& v, SpmvPlan& p, const double* val, cons
     if (!q) return hipErrorInvalidConfiguration;
     const unsigned rgrid = (unsigned)(8 * ((q->nb + 7) / 8));
     if (!values_ready && q->places > 0) {
-        hipLaunchKernelGGL(k_xs_permute, dim3(rgrid), dim3(kRedThreads), 0, s, q->nb, q->ns,
-                           q->places, p.row_ptr, q->rb, q->off, q->bk, val, q->bval);
+        hipLaunchKernelGGL(k_xs_permute, dim3(rgrid), dim3(kRedThreads), 0, s, q->nb, q->places,
+                           q->kbt, q->ej, q->bke, val, q->bval);
     }
     if (q->places > 0) {
         if (swl == 14)
             hipLaunchKernelGGL(k_xs_products<14>, dim3((unsigned)q->chunks), dim3(kProdThreads), 0,
-                               s, q->ncols, q->ns, q->nb, q->off, q->chunk_first, q->bcol, q->bval,
-                               x, q->prod);
+                               s, q->ncols, q->chunk_table, q->bcol, q->bval, x, q->prod);
         else
             hipLaunchKernelGGL(k_xs_products<13>, dim3((unsigned)q->chunks), dim3(kProdThreads), 0,
-                               s, q->ncols, q->ns, q->nb, q->off, q->chunk_first, q->bcol, q->bval,
-                               x, q->prod);
+                               s, q->ncols, q->chunk_table, q->bcol, q->bval, x, q->prod);
     }
-    hipLaunchKernelGGL(k_xs_reduce, dim3(rgrid), dim3(kRedThreads), 0, s, p.n, q->nb, q->ns,
-                       (int64_t)std::max<int64_t>(q->places, 1), p.row_ptr, q->rb, q->off, q->bk, q->prod, q->unit_ptr, q->uinfo, x, y, ep);
+    hipLaunchKernelGGL(k_xs_reduce, dim3(rgrid), dim3(kRedThreads), 0, s, p.n, q->nb,
+                       (int64_t)std::max<int64_t>(q->places, 1), q->rb, q->ub, q->kbt, q->ej,
+                       q->bke, q->prod, q->uinfo, x, y, ep);
     return hipGetLastError();
 }
 
@@ -606,14 +716,19 @@ void SpmvPlan::XSlice::release() {
     if (rb) hipFree(rb);
     if (off) hipFree(off);
     if (unit_ptr) hipFree(unit_ptr);
-    if (chunk_first) hipFree(chunk_first);
+    if (chunk_table) hipFree(chunk_table);
+    if (ej) hipFree(ej);
+    if (bke) hipFree(bke);
+    if (ub) hipFree(ub);
+    if (kbt) hipFree(kbt);
     if (bcol) hipFree(bcol);
-    if (bk) hipFree(bk);
     if (uinfo) hipFree(uinfo);
     if (bval) hipFree(bval);
     if (prod) hipFree(prod);
-    rb = off = unit_ptr = chunk_first = nullptr;
-    bcol = bk = nullptr;
+    rb = off = unit_ptr = ub = kbt = ej = nullptr;
+    bke = nullptr;
+    chunk_table = nullptr;
+    bcol = nullptr;
     uinfo = nullptr;
     bval = prod = nullptr;
 }
