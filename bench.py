@@ -2,7 +2,7 @@
 
 Workload: the size sweep -- cubic FP64 grids 16^3 .. 512^3, 20 sweeps each,
 u0 ~ U[0,1) (seed 2000 + log2 n), device-resident, one region with 10
-variants (5 GPU block / tile shapes, 5 host-CPU tilings).  Set-up
+variants (6 GPU kernels and block / tile shapes, 5 host-CPU tilings).  Set-up
 (untimed): the cost model is trained on the GPU from the method's own
 RoundRobin-profiled runs over 2000 random shapes and judged on 300 held-out
 shapes timed exhaustively; every variant is timed at every size (the
@@ -236,7 +236,7 @@ def kernel_only(variant: int, launches: int = 5):
 
 # the variant the learned selector picks at each size of the sweep (the
 # exhaustive best as well in the recorded runs); the trace mode replays them
-SWEEP_PICKS = {16: 1, 32: 0, 64: 1, 128: 4, 256: 2, 512: 3}
+SWEEP_PICKS = {16: 5, 32: 0, 64: 1, 128: 4, 256: 2, 512: 3}
 
 
 def trace_steps(steps: int, warmup: int):
@@ -374,8 +374,9 @@ def batch_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps * 1e-3, (time.perf_counter() - t0) / steps
 
-    region = ao.region_declare_variants("bench_batch_single", ao.AO_JACOBI7_F64,
-                                        ao.jacobi_variants_sweep()[:5], model_type="roundrobin")
+    gpu_variants = ao.jacobi_sweep_gpu()
+    region = ao.region_declare_variants("bench_batch_single", ao.AO_JACOBI7_F64, gpu_variants,
+                                        model_type="roundrobin")
 
     def per_instance(v):
         def fn():
@@ -383,7 +384,7 @@ def batch_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
                 ao.region_run(region, a, stream=stream, variant=v)
         return fn
     single = {}
-    for v in range(5):
+    for v in range(len(gpu_variants)):
         single[v] = timed(per_instance(v))
     b = ao.batch_create(ins)
     t_default_eager = timed(lambda: ao.batch_run(b, stream=stream, use_graph=False))
@@ -899,7 +900,10 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    V = 10
+    variants = ao.jacobi_variants_sweep()
+    V = len(variants)
+    gpu_ids = [v for v in range(V) if variants[v].target == ao.AO_TARGET_GPU]
+    host_ids = [v for v in range(V) if variants[v].target != ao.AO_TARGET_GPU]
     region = ao.region_declare_variants("bench_size_sweep", ao.AO_JACOBI7_F64,
                                         ao.jacobi_variants_sweep(), min_train_data=10 ** 9,
                                         model_type="mlp")
@@ -936,7 +940,7 @@ def main():
         a = ao.jacobi_args(u0, out, n, n, n, SWEEPS)
         med = []
         for v in range(V):
-            gpu = v < 5
+            gpu = v in gpu_ids
             med.append(ao.region_profile(region, a, variant=v, warmup=2 if gpu else 0,
                                          reps=5 if gpu else 1, stream=stream))
         table[n] = med
@@ -952,7 +956,7 @@ def main():
         a = ao.jacobi_args(hu, ho, n, n, n, SWEEPS, resident=0)
         med = []
         for v in range(V):
-            gpu = v < 5
+            gpu = v in gpu_ids
             med.append(ao.region_profile(region, a, variant=v, warmup=1 if gpu else 0,
                                          reps=3 if gpu else 1, stream=stream))
         table_host[n] = med
@@ -996,7 +1000,7 @@ def main():
     regret = {n: table[n][chosen[n]] / table[n][best[n]] - 1.0 for n in SIZES}
 
     nbig = SIZES[-1]
-    vbig = ao.jacobi_variants_sweep()[chosen[nbig]]
+    vbig = variants[chosen[nbig]]
     # launches of the region at the largest size: one per sweep, or one per
     # P fused sweeps (P = 2, 3, 4 for the temporally blocked families; the
     # S mod P remaining sweeps take one more launch)
@@ -1027,8 +1031,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "7-point FP64 Jacobi size sweep, cubic grids 16^3..512^3, 20 sweeps, "
-                               "device-resident, learned selection among 10 variants "
-                               "(5 GPU shapes + 5 host-CPU tilings)",
+                               "device-resident, learned selection among 11 variants "
+                               "(6 GPU kernels / shapes + 5 host-CPU tilings)",
                    "sizes": SIZES, "sweeps": SWEEPS},
         "value_meaning": "algorithmic bytes (16 B per point per sweep) over the region time",
         "algorithmic_rate_pct_of_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
@@ -1075,8 +1079,8 @@ def main():
         for n in SIZES:
             alg = 16.0 * n ** 3 * SWEEPS
             g = [alg / t / 1e9 for t in tab[n]]
-            bg = max(range(5), key=lambda v: g[v])
-            bh = max(range(5, V), key=lambda v: g[v])
+            bg = max(gpu_ids, key=lambda v: g[v])
+            bh = max(host_ids, key=lambda v: g[v])
             out[str(n)] = {"gbs_per_variant": [round(x, 2) for x in g],
                            "best_gpu": bg, "best_gpu_gbs": round(g[bg], 2),
                            "best_host": bh, "best_host_gbs": round(g[bh], 2),
@@ -1087,7 +1091,7 @@ def main():
         """Smallest size from which the best GPU variant stays ahead of the best host one."""
         first = None
         for n in reversed(SIZES):
-            if min(tab[n][:5]) < min(tab[n][5:]):
+            if min(tab[n][v] for v in gpu_ids) < min(tab[n][v] for v in host_ids):
                 first = n
             else:
                 break

@@ -83,9 +83,10 @@ enum ao_target { AO_TARGET_GPU = 0, AO_TARGET_HOST = 1 };
 
 enum ao_family {
     AO_FAM_JACOBI_DIRECT = 0, /* GPU: one thread per point, block bx*by (bx*by a multiple
-                                 of 64, at most 1024); a grid of at most 8192 points
-                                 runs all its sweeps in one launch of one workgroup
-                                 that holds the grid twice in LDS */
+                                 of 64, at most 1024); with AO_VF_LDS_SWEEPS a grid
+                                 of at most 8192 points runs all its sweeps in one
+                                 launch of one 1024-thread workgroup that holds the
+                                 grid twice in LDS */
     AO_FAM_JACOBI_ZMARCH = 1, /* GPU: bx*by LDS plane tile + halo, marches bz planes */
     AO_FAM_JACOBI_HOST = 2,   /* host CPU (OpenMP): tiles bx (0 = whole row) by by rows */
     AO_FAM_JACOBI_ZREG = 3,   /* GPU: register z-march, strip bx (64|128) wide, by (1|2|4|8)
@@ -131,6 +132,10 @@ enum ao_family {
                                  three and four, as soon as the first fused sweep has
                                  consumed the current plane) */
 #define AO_VF_OCCUPANCY 4     /* two-sweep z-march: registers capped for 4 waves per SIMD */
+#define AO_VF_LDS_SWEEPS 16   /* one-point-per-thread family: a grid of at most 8192
+                                 points runs all its sweeps in one workgroup's LDS
+                                 (larger grids run the family's kernel with the
+                                 variant's block shape) */
 #define AO_VF_STAGED 8        /* three- and four-sweep z-marches (not with
                                  AO_VF_HALO_PREFETCH): waves receive level 0 through
                                  asynchronous global->LDS copies one plane ahead (32-64

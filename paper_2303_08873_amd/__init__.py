@@ -12,7 +12,7 @@ from __future__ import annotations
 from ._lib import (  # noqa: F401
     AO_CSR_RELAX_F64, AO_CSR_SPMV_F64, AO_JACOBI7_F64, AO_MAX_FEATURES, AO_MAX_VARIANTS, AO_MLP_PARAMS,
     AO_OK, AO_NOTE_FALLBACK, AO_NOTE_UNTRAINED, AO_PROFILE_RECORD, AO_TARGET_GPU,
-    AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_OCCUPANCY, AO_VF_STAGED,
+    AO_TARGET_HOST, AO_VF_HALO_PREFETCH, AO_VF_NT_STORE, AO_VF_OCCUPANCY, AO_VF_STAGED, AO_VF_LDS_SWEEPS,
     FAM_JACOBI_DIRECT,
     FAM_JACOBI_HOST, FAM_JACOBI_ZMARCH, FAM_JACOBI_ZREG, FAM_JACOBI_ZREG_T2, FAM_JACOBI_ZREG_T3,
     FAM_JACOBI_ZREG_T4, FAM_JACOBI_COSCHED,
@@ -24,4 +24,4 @@ from ._lib import (  # noqa: F401
     region_record, region_records, region_run, region_run_noalloc, region_save, region_stats, selector_select, selector_train,
     jacobi_args, relax_args, spmv_args)
 from .variants import (  # noqa: F401
-    jacobi_variants_blocks, jacobi_variants_sweep, spmv_variants)
+    jacobi_sweep_gpu, jacobi_sweep_host, jacobi_variants_blocks, jacobi_variants_sweep, spmv_variants)

@@ -23,6 +23,7 @@ AO_VF_NT_STORE = 1
 AO_VF_HALO_PREFETCH = 2
 AO_VF_OCCUPANCY = 4
 AO_VF_STAGED = 8
+AO_VF_LDS_SWEEPS = 16
 AO_PROFILE_RECORD = 1
 
 _STATUS = {-1: "AO_EINVAL", -2: "AO_ENOMEM", -3: "AO_EHIP", -4: "AO_ESTATE", -5: "AO_EEXIST",

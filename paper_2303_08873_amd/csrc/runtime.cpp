@@ -188,6 +188,9 @@ int validate_variant(int kind, const ao_variant& v, int id) {
             (v.bx != 64 || !t2_rows_ok(v.by) || v.bz <= 0))
             return fail(AO_EINVAL,
                         at + "two-sweep z-march needs bx 64, by 1|2|3|4|6|8|10|12|16, bz > 0");
+        if ((v.flags & AO_VF_LDS_SWEEPS) && v.family != AO_FAM_JACOBI_DIRECT)
+            return fail(AO_EINVAL, at + "all sweeps in LDS is a flag of the one-point-per-thread "
+                                        "family");
         if ((v.flags & AO_VF_STAGED) &&
             ((v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4) ||
              (v.flags & AO_VF_HALO_PREFETCH)))
@@ -515,9 +518,9 @@ int run_cosched(ao_region* r, const ao_variant& v, const ao_args* a, hipStream_t
 // sweep, or (families fusing P = 2, 3 or 4 sweeps per pass) one per P
 // sweeps, the S mod P remaining sweeps first as one single register
 // z-march sweep, one two-sweep or one three-sweep pass.  The one-point-per-
-// thread family runs a grid of at most 8192 points in one workgroup's LDS,
-// all S sweeps in one launch (only for a block shape its sweep kernel
-// accepts).
+// thread family with AO_VF_LDS_SWEEPS runs a grid of at most 8192 points in
+// one workgroup's LDS, all S sweeps in one launch (only for a block shape
+// its sweep kernel accepts).
 struct JacobiPlan {
     int P = 1;            // sweeps per full launch
     int rem = 0;          // sweeps of the first launch when S mod P != 0
@@ -532,7 +535,8 @@ JacobiPlan jacobi_plan(const ao_variant& v, int nx, int ny, int nz, int S) {
           : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4
                                               : 1;
     p.rem = S % p.P;
-    p.lds_all = v.family == AO_FAM_JACOBI_DIRECT && S >= 1 && lds_sweeps_fit(nx, ny, nz) &&
+    p.lds_all = v.family == AO_FAM_JACOBI_DIRECT && (v.flags & AO_VF_LDS_SWEEPS) && S >= 1 &&
+                lds_sweeps_fit(nx, ny, nz) &&
                 v.bx > 0 && v.by > 0 && (int64_t)v.bx * v.by <= 1024 && (v.bx * v.by) % 64 == 0;
     p.launches = S == 0 ? 0 : p.lds_all ? 1 : S / p.P + (p.rem ? 1 : 0);
     return p;

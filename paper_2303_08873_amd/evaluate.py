@@ -70,7 +70,7 @@ def shape_features(dims, sweeps, resident):
             float(sweeps), math.log2(16.0 * n * int(sweeps)), float(resident)]
 
 
-def collect_training(region, bufs, n_train, seed, max_dim, stream, V=10):
+def collect_training(region, bufs, n_train, seed, max_dim, stream, V):
     """The method's own training data: every training shape runs V times
     under RoundRobin exploration, each run profiled and recorded.  Returns
     the seconds it took."""
@@ -92,7 +92,7 @@ def collect_training(region, bufs, n_train, seed, max_dim, stream, V=10):
     return time.perf_counter() - t0
 
 
-def held_out_table(region, bufs, n_test, seed, max_dim, warmup, reps, stream, V=10):
+def held_out_table(region, bufs, n_test, seed, max_dim, warmup, reps, stream, V):
     """Exhaustive table of the held-out shapes (every variant, `warmup`
     runs then the median of `reps`; not recorded) and their features."""
     import synth
@@ -164,7 +164,7 @@ def run(n_train=2000, n_test=2000, train_seed=4, test_seed=40, max_dim=512, warm
 
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream(dev)
-    V = 10
+    V = len(jacobi_variants_sweep())
     bufs = ShapeBuffers(max_dim, dev)
     region = ao.region_declare_variants(f"eval_{train_seed}_{n_train}", ao.AO_JACOBI7_F64,
                                         jacobi_variants_sweep(), min_train_data=10 ** 9,

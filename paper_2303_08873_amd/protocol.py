@@ -19,7 +19,7 @@ every input timed: warmup 1, median of 5):
   as many unique samples as variants, and uses the model for the remaining
   iterations (Sec. 4 "GPU threads", Online).  This one runs the library's
   own region_run loop on the inputs and sums the recorded times; it is run
-  over all 10 variants and over the 5 GPU variants alone (the paper's
+  over all variants and over the GPU variants alone (the paper's
   GPU-threads setting, where exploring costs little).
 
 Models: the library's MLP cost model (GPU-trained) and the paper's depth-2
@@ -172,10 +172,11 @@ def run(n_inputs=1000, n_online=100, iters=100, seed=40, max_dim=512, epochs=200
             _log(f"Adaptive-{25 * m} {model}: {result[f'adaptive_{25 * m}_{model}']}")
 
     # Online: the library's own explore -> train -> exploit loop per input,
-    # over all 10 variants (exploration includes the host variants) and over
-    # the 5 GPU variants alone (the paper's GPU-threads setting)
+    # over all variants (exploration includes the host variants) and over
+    # the GPU variants alone (the paper's GPU-threads setting)
     online = {}
-    for vset_name, vids in (("all_variants", list(range(V))), ("gpu_variants", list(range(5)))):
+    gpu_ids = [v for v in range(V) if variants[v].target == ao.AO_TARGET_GPU]
+    for vset_name, vids in (("all_variants", list(range(V))), ("gpu_variants", gpu_ids)):
         for model in ("mlp", "dtree"):
             tot, tot_static, tot_best, per = 0.0, 0.0, 0.0, []
             picks_best = 0

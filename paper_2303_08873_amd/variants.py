@@ -3,7 +3,7 @@ as categorical variants are numbered from 0 in the order given, Sec. 3.1
 model_output clause)."""
 from __future__ import annotations
 
-from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_NT_STORE, AO_VF_STAGED,
+from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_LDS_SWEEPS, AO_VF_NT_STORE, AO_VF_STAGED,
                    FAM_JACOBI_DIRECT, FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T3,
                    FAM_JACOBI_ZREG_T4, FAM_SPMV_XSLICE,
                    FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, Variant)
@@ -17,24 +17,36 @@ def jacobi_variants_blocks():
             Variant(AO_TARGET_GPU, FAM_JACOBI_DIRECT, 64, 16, 1, 0)]
 
 
-# ids 0..4 run on the GPU, 5..9 on the host CPU (device-selection use case)
+# ids 0..5 run on the GPU, 6..10 on the host CPU (device-selection use case)
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_ZREG_T3, 64, 1, 1, AO_VF_STAGED), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
                     (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED),
                     (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED),
-                    (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED)]
+                    (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED),
+                    (FAM_JACOBI_DIRECT, 64, 16, 1, AO_VF_LDS_SWEEPS)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
 STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
 
 
 def jacobi_variants_sweep():
-    """10 variants: 5 GPU block / tile shapes (one point per thread with
-    64x4 threads; the register z-march with three or four sweeps per pass,
-    level 0 staged: 1 row per wave and 1 plane per block for small grids,
-    4 rows per wave and 4, 22 or 74 planes per block) and 5 host-CPU
-    cache-block shapes."""
+    """11 variants: 6 GPU kernels (the three-sweep register z-march with
+    level 0 staged, 1 row per wave and 1 plane per block for small grids;
+    one point per thread with 64x4 threads, the static default; three- and
+    four-sweep marches with 4 rows per wave and 22, 74 or 4 planes per
+    block; one point per thread with 64x16 threads and small grids' sweeps
+    all in one workgroup's LDS) and 5 host-CPU cache-block shapes."""
     out = [Variant(AO_TARGET_GPU, f, bx, by, bz, fl) for f, bx, by, bz, fl in JACOBI_SWEEP_GPU]
     out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]
     return out
+
+
+def jacobi_sweep_gpu():
+    """The GPU variants of the size-sweep table (its first ids)."""
+    return jacobi_variants_sweep()[:len(JACOBI_SWEEP_GPU)]
+
+
+def jacobi_sweep_host():
+    """The host-CPU variants of the size-sweep table (its last ids)."""
+    return jacobi_variants_sweep()[len(JACOBI_SWEEP_GPU):]
 
 
 def spmv_variants(blocks=(64, 256, 1024), wave_lanes: int = 64, xslice=()):

@@ -76,7 +76,7 @@ def test_library_tree_matches_oracle(orc, seed, depth):
             recs.append((f, v, float(math.exp(0.3 * base[v] + 0.2 * noise[v]))))
     mt = "dtree" if depth == 2 else f"dtree,{depth}"
     h = ao.region_declare_variants(f"dt_{seed}_{depth}", ao.AO_JACOBI7_F64,
-                                   ao.jacobi_variants_sweep()[5:], min_train_data=10 ** 6,
+                                   ao.jacobi_sweep_host(), min_train_data=10 ** 6,
                                    model_type=mt)
     for f, v, t in recs:
         ao.region_record(h, f, v, t)

@@ -325,10 +325,10 @@ def test_full_size_512_every_variant_against_the_oracle(env, orc):
     u0 = synth.grid_u01_torch(n, n, n, seed=2009, device=dev)
     want = torch.from_numpy(orc.jacobi7(u0.cpu().numpy(), n, n, n, S)).to(dev)
     out = torch.empty_like(u0)
-    h = ao.region_declare_variants("gpu_full", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep()[:5],
-                                   model_type="roundrobin")
+    gpu = ao.jacobi_sweep_gpu()
+    h = ao.region_declare_variants("gpu_full", ao.AO_JACOBI7_F64, gpu, model_type="roundrobin")
     a = ao.jacobi_args(u0, out, n, n, n, S)
-    for v in range(5):
+    for v in range(len(gpu)):
         out.fill_(-1.0)
         ao.region_run(h, a, stream=st, variant=v)
         torch.cuda.synchronize()
@@ -343,18 +343,19 @@ def test_full_size_512_every_variant_against_the_oracle(env, orc):
 @pytest.mark.parametrize("shape,S", [((16, 16, 32), 7), ((8193, 1, 1), 2), ((1, 8192, 1), 3),
                                      ((20, 20, 20), 1), ((3, 5, 7), 20), ((16, 16, 33), 2)])
 def test_direct_family_small_grids_in_lds(env, orc, shape, S):
-    # grids of at most 8192 points run all sweeps in one workgroup's LDS
-    # (16x16x32, 1x8192x1, 20^3, 3x5x7); 8193x1x1 and 16x16x33 just past the
-    # limit take the per-sweep launches; both residencies, bit-identical to
-    # the oracle
+    # with the all-sweeps-in-LDS flag, grids of at most 8192 points run all
+    # sweeps in one workgroup's LDS (16x16x32, 1x8192x1, 20^3, 3x5x7);
+    # 8193x1x1 and 16x16x33 just past the limit, and every grid without the
+    # flag, take the per-sweep launches of the block shape; both
+    # residencies, bit-identical to the oracle
     ao, torch, dev, st = env
     nx, ny, nz = shape
     u0_h = synth.grid_u01(nx, ny, nz, seed=91 + nz + S)
     want = orc.jacobi7(u0_h, nx, ny, nz, S)
     u0 = torch.from_numpy(u0_h).to(dev)
     out = torch.empty_like(u0)
-    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, bx, by, 1, 0)
-          for bx, by in ((64, 4), (32, 8), (64, 16))]
+    vs = [ao.Variant(ao.AO_TARGET_GPU, ao.FAM_JACOBI_DIRECT, bx, by, 1, fl)
+          for fl in (0, ao.AO_VF_LDS_SWEEPS) for bx, by in ((64, 4), (32, 8), (64, 16))]
     h = ao.region_declare_variants(f"gpu_lds_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
                                    model_type="roundrobin")
     for resident in (1, 0):

@@ -110,5 +110,6 @@ def test_exhaustive_producer_picks_the_profiled_minimum(env):
         per.setdefault(var, []).append(s)
     med = {k: float(np.median(x)) for k, x in per.items()}
     assert v == min(med, key=lambda k: (med[k], k))
-    assert v < 5   # a device-resident 96^3 grid is faster on the GPU than on the host
+    # a device-resident 96^3 grid is faster on the GPU than on the host
+    assert ao.jacobi_variants_sweep()[v].target == ao.AO_TARGET_GPU
     ao.region_destroy(h)

@@ -35,7 +35,7 @@ def test_header_symbols_exported(ao):
 
 
 def _host_region(ao, name, model_type="roundrobin", min_train=0):
-    vs = ao.jacobi_variants_sweep()[5:]
+    vs = ao.jacobi_sweep_host()
     return ao.region_declare_variants(name, ao.AO_JACOBI7_F64, vs, min_train, model_type)
 
 
@@ -86,7 +86,7 @@ def test_roundrobin_and_trigger_follow_oracle(ao, orc):
 
 
 def test_declare_idempotent_and_conflict(ao):
-    vs = ao.jacobi_variants_sweep()[5:]
+    vs = ao.jacobi_sweep_host()
     h1 = ao.region_declare_variants("idem", ao.AO_JACOBI7_F64, vs)
     h2 = ao.region_declare_variants("idem", ao.AO_JACOBI7_F64, vs)
     assert h1.value == h2.value
@@ -113,7 +113,7 @@ def test_argument_errors(ao):
     with pytest.raises(ao.AdaptError):
         ao.region_declare_variants("badvar", ao.AO_JACOBI7_F64, [bad])
     with pytest.raises(ao.AdaptError):
-        ao.region_declare_variants("badtype", ao.AO_JACOBI7_F64, [ao.jacobi_variants_sweep()[5]],
+        ao.region_declare_variants("badtype", ao.AO_JACOBI7_F64, [ao.jacobi_sweep_host()[0]],
                                    model_type="forest")
     with pytest.raises(ao.AdaptError):
         ao.region_declare_variants("toomany", ao.AO_JACOBI7_F64, ao.jacobi_variants_sweep() * 2)
@@ -181,7 +181,7 @@ def test_save_load_roundtrip_and_corruption(ao, tmp_path):
     with pytest.raises(ao.AdaptError):
         ao.region_load(h2, str(tmp_path / "missing.bin"))
     other = ao.region_declare_variants("persist_other", ao.AO_JACOBI7_F64,
-                                       ao.jacobi_variants_sweep()[5:8])
+                                       ao.jacobi_sweep_host()[:3])
     with pytest.raises(ao.AdaptError):
         ao.region_load(other, path)
     for x in (h, h2, other):
@@ -275,7 +275,7 @@ def test_relax_argument_errors(ao):
     ao.region_destroy(h)
     with pytest.raises(ao.AdaptError):   # relaxation variants run on the GPU
         ao.region_declare_variants("relax_host", ao.AO_CSR_RELAX_F64,
-                                   [ao.jacobi_variants_sweep()[5]])
+                                   [ao.jacobi_sweep_host()[0]])
 
 
 def test_xslice_spmv_variant_validation(ao):
@@ -311,3 +311,23 @@ def test_stencil_features_match_oracle(ao, orc, resident):
         want = orc.stencil_features(nx, ny, nz, S, resident)
         assert got.tobytes() == want.tobytes(), ((nx, ny, nz, S), got, want)
     ao.region_destroy(h)
+
+
+def test_lds_sweeps_flag_only_on_the_direct_family(ao):
+    G = ao.AO_TARGET_GPU
+    ok = ao.region_declare_variants("lds_flag_ok", ao.AO_JACOBI7_F64,
+                                    [ao.Variant(G, ao.FAM_JACOBI_DIRECT, 64, 16, 1,
+                                                ao.AO_VF_LDS_SWEEPS)])
+    ao.region_destroy(ok)
+    with pytest.raises(ao.AdaptError):
+        ao.region_declare_variants("lds_flag_bad", ao.AO_JACOBI7_F64,
+                                   [ao.Variant(G, ao.FAM_JACOBI_ZREG_T3, 64, 4, 4,
+                                               ao.AO_VF_LDS_SWEEPS)])
+    # the size-sweep table: the static default is the plain 256-thread kernel
+    vs = ao.jacobi_variants_sweep()
+    from paper_2303_08873_amd.variants import STATIC_DEFAULT
+    d = vs[STATIC_DEFAULT]
+    assert (d.family, d.bx * d.by, d.flags) == (ao.FAM_JACOBI_DIRECT, 256, 0)
+    assert len(ao.jacobi_sweep_gpu()) + len(ao.jacobi_sweep_host()) == len(vs)
+    assert all(v.target == G for v in ao.jacobi_sweep_gpu())
+    assert all(v.target == ao.AO_TARGET_HOST for v in ao.jacobi_sweep_host())

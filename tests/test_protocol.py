@@ -48,7 +48,7 @@ def test_online_loop_explores_then_exploits_on_host(orc):
     # first 5 runs explore RoundRobin, the 5th trains, the rest use the
     # fastest explored variant; every output equals the oracle
     import paper_2303_08873_amd as ao
-    vs = ao.jacobi_variants_sweep()[5:]
+    vs = ao.jacobi_sweep_host()
     h = ao.region_declare_variants("online_host", ao.AO_JACOBI7_F64, vs, model_type="dtree")
     nx, ny, nz, S = 24, 20, 18, 3
     u0 = synth.grid_u01(nx, ny, nz, seed=11)
