@@ -70,7 +70,9 @@ def _scale(m):
 
 
 @pytest.mark.parametrize("n,mean,max_len,seed", [(3000, 16.0, 300, 50), (700, 4.0, 700, 51),
-                                                 (5000, 64.0, 4096, 52), (257, 16.0, 257, 53)])
+                                                 (5000, 64.0, 4096, 52), (257, 16.0, 257, 53),
+                                                 (40000, 1.5, 40, 54)])  # last: mostly
+# one-nonzero rows, so an x-slice row block holds more units than threads
 def test_pareto_matrices(env, orc, n, mean, max_len, seed):
     ao, torch, dev, st = env
     m = synth.csr_matrix(n, seed, mean=mean, max_len=max_len)
