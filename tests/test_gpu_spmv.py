@@ -69,10 +69,11 @@ def _scale(m):
     return cs[rp[1:].astype(np.int64)] - cs[rp[:-1].astype(np.int64)]
 
 
+# (the last case: mostly one-nonzero rows, so an x-slice row block holds
+# more units than its workgroup has threads)
 @pytest.mark.parametrize("n,mean,max_len,seed", [(3000, 16.0, 300, 50), (700, 4.0, 700, 51),
                                                  (5000, 64.0, 4096, 52), (257, 16.0, 257, 53),
-                                                 (40000, 1.5, 40, 54)])  # last: mostly
-# one-nonzero rows, so an x-slice row block holds more units than threads
+                                                 (40000, 1.5, 40, 54)])
 def test_pareto_matrices(env, orc, n, mean, max_len, seed):
     ao, torch, dev, st = env
     m = synth.csr_matrix(n, seed, mean=mean, max_len=max_len)
