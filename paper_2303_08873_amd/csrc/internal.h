@@ -73,9 +73,10 @@ struct SpmvPlan {
         int4* chunk_table = nullptr;    // [chunks] (slice, first place, end place, 0) per products workgroup
         int chunks = 0;
         uint16_t* bcol = nullptr;       // [places] column inside the slice
-        int32_t* ej = nullptr;          // [places] per element (a block's places in place order,
-                                        // blocks in row order): its place
-        uint16_t* bke = nullptr;        // [places] per element: its nonzero's index inside the block
+        int32_t* ej = nullptr;          // [nb * DCAP] per element slot (block t's places in place
+                                        // order from t * DCAP; unused slots 0): its place
+        uint16_t* bke = nullptr;        // [nb * DCAP] per element slot: its nonzero's index inside
+                                        // the block
         uint64_t* uinfo = nullptr;      // [units] unit descriptors (first nonzero and count, the
                                         // row's unit count, row inside the block, index in the row)
         int32_t* ub = nullptr;          // [nb + 1] first unit of each block

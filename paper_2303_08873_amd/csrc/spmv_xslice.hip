@@ -158,9 +158,11 @@ __global__ __launch_bounds__(256) void k_xs_slice_starts(int nb, int ns,
 // time; a lane's place is its slice's cursor plus the number of earlier
 // lanes of the chunk in the same slice, so each piece keeps CSR order.
 // The block's elements are its places in place order (its pieces one
-// after the other): element e of block t sits at index kbt[t] - k0 + e of
-// the element arrays, which hold its place (ej) and its nonzero's index
-// inside the block (bke, the LDS slot it is summed in).
+// after the other): element e of block t sits at index t * DCAP + e of the
+// element arrays (a fixed stride, so a workgroup can request its elements
+// before it knows how many there are; unused slots hold zeros), which hold
+// its place (ej) and its nonzero's index inside the block (bke, the LDS
+// slot it is summed in).
 __global__ __launch_bounds__(64) void k_xs_place(int nb, int ns, int sw,
                                                  const int32_t* __restrict__ row_ptr,
                                                  const int32_t* __restrict__ col,
@@ -192,7 +194,6 @@ __global__ __launch_bounds__(64) void k_xs_place(int nb, int ns, int sw,
         carry += __shfl(v, 63);
     }
     __syncthreads();
-    const int32_t k0 = row_ptr[0];
     const int32_t kb = row_ptr[rb[t]], ke = row_ptr[rb[t + 1]];
     for (int32_t c = kb; c < ke; c += 64) {
         const int32_t k = c + lane;
@@ -216,9 +217,9 @@ __global__ __launch_bounds__(64) void k_xs_place(int nb, int ns, int sw,
         if (live) {
             const int64_t j = (int64_t)base + before;
             const int64_t e = (int64_t)eb + (j - st);   // element index inside the block
-            const int64_t x = (int64_t)(kb - k0) + e;   // its slot in the element arrays
+            const int64_t x = (int64_t)t * kDCAP + e;   // its slot in the element arrays
             if (j >= 0 && j < places) bcol[j] = (uint16_t)(cc - (s << sw));
-            if (x >= 0 && x < places) {
+            if (e >= 0 && e < kDCAP) {
                 ej[x] = (int32_t)j;
                 bke[x] = (uint16_t)(k - kb);
             }
@@ -293,8 +294,41 @@ __device__ __forceinline__ int xcd_block(int g, int nb) {
 // issues all their loads together.
 constexpr int kPer = kDCAP / kRedThreads;
 
+// The element slots of row block t a thread takes (e = thread + q * threads):
+// the first half is requested at once, at the block's fixed offset; the
+// second half only when the block's count (`count()`, which may wait on a
+// load) says it has more elements than that.  Slots past the count hold
+// zeros; the caller discards them.  (The slots' 16-bit fields land in
+// 32-bit registers of their own: packing two into one register would make
+// the code wait for the loads right here.)
+template <typename Count>
+__device__ __forceinline__ void load_elements(int t, const int32_t* __restrict__ ej,
+                                              const uint16_t* __restrict__ bke, int32_t* j,
+                                              int32_t* b, Count count) {
+    const int64_t xt = (int64_t)t * kDCAP + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kPer / 2; ++q) {
+        j[q] = ej[xt + q * kRedThreads];
+        b[q] = bke[xt + q * kRedThreads];
+    }
+    if (count() > kDCAP / 2) {  // workgroup-uniform
+#pragma unroll
+        for (int q = kPer / 2; q < kPer; ++q) {
+            j[q] = ej[xt + q * kRedThreads];
+            b[q] = bke[xt + q * kRedThreads];
+        }
+    } else {
+#pragma unroll
+        for (int q = kPer / 2; q < kPer; ++q) {
+            j[q] = 0;
+            b[q] = 0;
+        }
+    }
+}
+
 // bval[ej[x]] = val[kb + bke[x]] over the elements x of each row block
-// (workgroup per row block)
+// (workgroup per row block; the first half of its element slots is
+// requested before its bounds)
 __global__ __launch_bounds__(kRedThreads) void k_xs_permute(int nb, int64_t places,
                                                             const int32_t* __restrict__ kbt,
                                                             const int32_t* __restrict__ ej,
@@ -303,17 +337,14 @@ __global__ __launch_bounds__(kRedThreads) void k_xs_permute(int nb, int64_t plac
                                                             double* __restrict__ bval) {
     const int t = xcd_block((int)blockIdx.x, nb);
     if (t >= nb) return;
-    const int32_t k0 = kbt[0], kb = kbt[t], kend = kbt[nb];
+    int32_t j[kPer], b[kPer];
+    load_elements(t, ej, bke, j, b, [&]() { return kbt[t + 1] - kbt[t]; });
+    const int32_t kb = kbt[t], kend = kbt[nb];
     const int total = min(kbt[t + 1] - kb, kDCAP);
-    const int64_t x0 = (int64_t)(kb - k0);
-    int32_t j[kPer];
-    uint16_t b[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int e = (int)threadIdx.x + q * kRedThreads;
-        const bool live = e < total;
-        j[q] = live ? min(max(ej[x0 + e], 0), (int32_t)(places - 1)) : -1;
-        b[q] = live ? bke[x0 + e] : (uint16_t)0;
+        j[q] = e < total ? min(max(j[q], 0), (int32_t)(places - 1)) : -1;
     }
     double v[kPer];
 #pragma unroll
@@ -450,22 +481,18 @@ __global__ __launch_bounds__(kRedThreads) void k_xs_reduce(int n, int nb, int64_
     if (t >= nb) return;
     // everything the block needs that does not depend on its products is
     // requested up front: its elements, its first row and its units
+    int32_t j[kPer], b[kPer];
+    load_elements(t, ej, bke, j, b, [&]() { return kbt[t + 1] - kbt[t]; });
     const int r0 = rb[t];
     const int32_t u0 = ub[t], u1 = ub[t + 1];
-    const int32_t k0 = kbt[0], kb = kbt[t];
-    const int total = min(kbt[t + 1] - kb, kDCAP);
-    const int64_t x0 = (int64_t)(kb - k0);
+    const int total = min(kbt[t + 1] - kbt[t], kDCAP);
     const int32_t uf = u0 + (int32_t)threadIdx.x;
     const uint64_t first = uf < u1 ? uinfo[uf] : 0;
     {
-        int32_t j[kPer];
-        uint16_t b[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int e = (int)threadIdx.x + q * kRedThreads;
-            const bool live = e < total;
-            j[q] = live ? min(max(ej[x0 + e], 0), (int32_t)(places - 1)) : -1;
-            b[q] = live ? bke[x0 + e] : (uint16_t)0;
+            j[q] = e < total ? min(max(j[q], 0), (int32_t)(places - 1)) : -1;
         }
         double v[kPer];
 #pragma unroll
@@ -653,8 +680,11 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
                       hipMemcpyHostToDevice);
     const size_t pl = (size_t)std::max<int64_t>(places, 1);
     if (e == hipSuccess) e = hipMalloc(&q.bcol, pl * 2);
-    if (e == hipSuccess) e = hipMalloc(&q.ej, pl * 4);
-    if (e == hipSuccess) e = hipMalloc(&q.bke, pl * 2);
+    const size_t slots = (size_t)nb * kDCAP;  // element slots: DCAP per row block
+    if (e == hipSuccess) e = hipMalloc(&q.ej, slots * 4);
+    if (e == hipSuccess) e = hipMalloc(&q.bke, slots * 2);
+    if (e == hipSuccess) e = hipMemsetAsync(q.ej, 0, slots * 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(q.bke, 0, slots * 2, s);
     if (e == hipSuccess) e = hipMalloc(&q.uinfo, (size_t)std::max<int64_t>(units, 1) * 8);
     if (e == hipSuccess) e = hipMalloc(&q.ub, (size_t)(nb + 1) * 4);
     if (e == hipSuccess) e = hipMalloc(&q.kbt, (size_t)(nb + 1) * 4);
