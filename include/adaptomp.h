@@ -114,14 +114,16 @@ enum ao_family {
     AO_FAM_SPMV_MERGE_PATH = 12, /* GPU: nnz-balanced row-aligned chunks, blocks of bx */
     AO_FAM_SPMV_XSLICE = 13      /* GPU: columns cut into slices of 2^by columns (by 13|14;
                                     0 = 14: 64 or 128 KB of x) and rows into blocks of at most
-                                    4096 nonzeros + rows; a per-matrix plan orders the
-                                    nonzeros slice by slice (about 8 B per nonzero plus 16 B
+                                    4096 nonzeros + rows (a block whose last row would take
+                                    it past 4096 nonzeros is split before that row); a
+                                    per-matrix plan orders the
+                                    nonzeros slice by slice (about 15 B per nonzero plus 16 B
                                     per nonzero of value and product arrays); per execution
                                     the values are copied into that order when they changed
                                     (see values_id), each slice's products are formed with x
                                     in LDS, and each row block sums its rows from the
                                     products in LDS; bx = 0 (fixed geometry); rows longer
-                                    than 4097 nonzeros are refused (AO_ELAUNCH, the variant
+                                    than 4608 nonzeros are refused (AO_ELAUNCH, the variant
                                     is masked for the region) */
 };
 

@@ -5,7 +5,10 @@
 // Infinity Cache.  This family makes every gather an LDS read instead.
 // Columns are cut into slices of SW = 2^sw columns (8K or 16K: 64 or 128 KB
 // of x), rows into blocks of at most DN = 4096 cost units (one per nonzero
-// and one per row; at most DCAP = 8192 nonzeros).  A per-matrix plan orders
+// and one per row), a block whose last row would carry it past SPEC = 4096
+// nonzeros being split before that row (so a block holds at most 4096
+// nonzeros, or a single row of at most DCAP = 4608; longer rows are
+// refused).  A per-matrix plan orders
 // the nonzeros slice by slice (slice outer, then block, then CSR order) and
 // keeps, per place, the column inside its slice and the position inside its
 // block (16 bits each).  One execution:
@@ -27,10 +30,11 @@
 namespace ao {
 namespace {
 
-constexpr int kDN = 4096;      // cost units (nonzeros + rows) per row block
-constexpr int kDCAP = 8192;    // nonzeros a row block can hold in LDS
+constexpr int kDN = 4096;      // cost units (nonzeros + rows) per cost block
+constexpr int kSpec = 4096;    // nonzeros of a row block of several rows
+constexpr int kDCAP = 4608;    // nonzeros a row block can hold in LDS (a single long row)
 constexpr int kMaxSlices = 1024;
-constexpr int kRedThreads = 1024;
+constexpr int kRedThreads = 512;  // 4 reduce workgroups (32 KB of LDS each) per CU
 constexpr int kProdThreads = 1024;
 constexpr int kProdChunk = 65536;  // places per products workgroup (target)
 
@@ -39,8 +43,8 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ---- plan ----------------------------------------------------------------
 
-// rb[t] = first row i whose cost (row_ptr[i] - row_ptr[0]) + i is >= t * DN
-// (the cost is strictly increasing in i); rb[nb] = n
+// Cost blocks: rb[t] = first row i whose cost (row_ptr[i] - row_ptr[0]) + i
+// is >= t * DN (the cost is strictly increasing in i); rb[nb] = n
 __global__ void k_xs_blocks(int n, int nb, const int32_t* __restrict__ row_ptr,
                             int32_t* __restrict__ rb) {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -57,6 +61,33 @@ __global__ void k_xs_blocks(int n, int nb, const int32_t* __restrict__ row_ptr,
         if ((int64_t)(row_ptr[mid] - k0) + mid >= target) hi = mid; else lo = mid + 1;
     }
     rb[t] = lo;
+}
+
+// Row blocks from cost blocks: a cost block [a, b) holds fewer than DN cost
+// units before its last row b - 1, so fewer than SPEC nonzeros there; when
+// the whole block holds more than SPEC nonzeros its last row becomes a block
+// of its own (at most DCAP nonzeros: longer rows are refused).  cnt[t] = 1
+// or 2 row blocks of cost block t.
+__global__ void k_xs_split_count(int nbc, const int32_t* __restrict__ row_ptr,
+                                 const int32_t* __restrict__ rbc, int32_t* __restrict__ cnt) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= nbc) return;
+    const int32_t a = rbc[t], b = rbc[t + 1];
+    cnt[t] = (b > a + 1 && row_ptr[b] - row_ptr[a] > kSpec) ? 2 : 1;
+}
+
+// rb (nb + 1 entries) from the cost blocks and the exclusive scan pos of cnt
+__global__ void k_xs_split_write(int nbc, int n, int nb, const int32_t* __restrict__ rbc,
+                                 const int32_t* __restrict__ cnt,
+                                 const int32_t* __restrict__ pos, int32_t* __restrict__ rb) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t > nbc) return;
+    if (t == nbc) {
+        rb[nb] = n;
+        return;
+    }
+    rb[pos[t]] = rbc[t];
+    if (cnt[t] == 2) rb[pos[t] + 1] = rbc[t + 1] - 1;
 }
 
 // *out = largest column index (the matrix may be rectangular: x can be
@@ -238,8 +269,9 @@ __global__ __launch_bounds__(1024) void k_xs_unit_counts(int n, const int32_t* _
     nu[i] = len > 0 ? (len + 63) / 64 : 1;
 }
 
-// Unit descriptors, 64 bits each, for the units of row i (its block t =
-// cost(i) / DN): bits 0-15 the unit's first nonzero inside the block, 16-23
+// Unit descriptors, 64 bits each, for the units of row i (its row block t:
+// the first row block of cost block cost(i) / DN, or the second when that
+// cost block was split and i is its last row): bits 0-15 the unit's first nonzero inside the block, 16-23
 // its nonzero count (0..64), 24-31 the row's unit count, 32-47 the row
 // inside the block, 48-63 the unit's index in the row.
 __device__ __forceinline__ uint64_t unit_desc(int a, int m, int nu, int r, int jn) {
@@ -250,10 +282,12 @@ __device__ __forceinline__ uint64_t unit_desc(int a, int m, int nu, int r, int j
 __global__ __launch_bounds__(256) void k_xs_units(int n, const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ unit_ptr,
                                                   const int32_t* __restrict__ rb,
+                                                  const int32_t* __restrict__ pos,
                                                   int64_t units, uint64_t* __restrict__ uinfo) {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
-    const int t = (int)(((int64_t)(row_ptr[i] - row_ptr[0]) + i) / kDN);
+    const int tc = (int)(((int64_t)(row_ptr[i] - row_ptr[0]) + i) / kDN);
+    const int t = pos[tc] + (i >= rb[pos[tc] + 1] ? 1 : 0);
     const int r = i - rb[t];
     const int32_t rs = row_ptr[i] - row_ptr[rb[t]];
     const int32_t len = row_ptr[i + 1] - row_ptr[i];
@@ -290,15 +324,16 @@ __device__ __forceinline__ int xcd_block(int g, int nb) {
 }
 
 // A row block holds at most DCAP elements; a thread of a kRedThreads-wide
-// workgroup takes elements e = thread + q * kRedThreads, q < kPer, and
-// issues all their loads together.
-constexpr int kPer = kDCAP / kRedThreads;
+// workgroup takes elements e = thread + q * kRedThreads, q < kPer.
+constexpr int kPer = (kDCAP + kRedThreads - 1) / kRedThreads;
+constexpr int kSpecPer = kSpec / kRedThreads;
+static_assert(kSpecPer * kRedThreads == kSpec && kPer * kRedThreads == kDCAP, "slot tiling");
 
-// The element slots of row block t a thread takes (e = thread + q * threads):
-// the first half is requested at once, at the block's fixed offset; the
-// second half only when the block's count (`count()`, which may wait on a
-// load) says it has more elements than that.  Slots past the count hold
-// zeros; the caller discards them.  (The slots' 16-bit fields land in
+// The element slots of row block t a thread takes: the first SPEC slots are
+// requested at once at the block's fixed offset, before its bounds arrive;
+// the rest only when the block's count (`count()`, which may wait on a
+// load) says it is a single row longer than SPEC.  Slots past the count
+// hold zeros; the caller discards them.  (The slots' 16-bit fields land in
 // 32-bit registers of their own: packing two into one register would make
 // the code wait for the loads right here.)
 template <typename Count>
@@ -307,19 +342,19 @@ __device__ __forceinline__ void load_elements(int t, const int32_t* __restrict__
                                               int32_t* b, Count count) {
     const int64_t xt = (int64_t)t * kDCAP + threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < kPer / 2; ++q) {
+    for (int q = 0; q < kSpecPer; ++q) {
         j[q] = ej[xt + q * kRedThreads];
         b[q] = bke[xt + q * kRedThreads];
     }
-    if (count() > kDCAP / 2) {  // workgroup-uniform
+    if (count() > kSpec) {  // workgroup-uniform
 #pragma unroll
-        for (int q = kPer / 2; q < kPer; ++q) {
+        for (int q = kSpecPer; q < kPer; ++q) {
             j[q] = ej[xt + q * kRedThreads];
             b[q] = bke[xt + q * kRedThreads];
         }
     } else {
 #pragma unroll
-        for (int q = kPer / 2; q < kPer; ++q) {
+        for (int q = kSpecPer; q < kPer; ++q) {
             j[q] = 0;
             b[q] = 0;
         }
@@ -327,8 +362,8 @@ __device__ __forceinline__ void load_elements(int t, const int32_t* __restrict__
 }
 
 // bval[ej[x]] = val[kb + bke[x]] over the elements x of each row block
-// (workgroup per row block; the first half of its element slots is
-// requested before its bounds)
+// (workgroup per row block; its first SPEC element slots are requested
+// before its bounds)
 __global__ __launch_bounds__(kRedThreads) void k_xs_permute(int nb, int64_t places,
                                                             const int32_t* __restrict__ kbt,
                                                             const int32_t* __restrict__ ej,
@@ -499,7 +534,7 @@ __global__ __launch_bounds__(kRedThreads) void k_xs_reduce(int n, int nb, int64_
         for (int q = 0; q < kPer; ++q) v[q] = j[q] >= 0 ? prod[j[q]] : 0.0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q)
-            if (j[q] >= 0) sl[b[q] & (kDCAP - 1)] = v[q];
+            if (j[q] >= 0) sl[min(b[q], kDCAP - 1)] = v[q];
     }
     __syncthreads();
     // one thread per unit: a row of one unit is finished here; the units of
@@ -534,7 +569,7 @@ __global__ __launch_bounds__(kRedThreads) void k_xs_reduce(int n, int nb, int64_
 
 // Largest row the family takes: a block holds at most DN - 1 cost units
 // before its last row starts, plus that row.
-int spmv_xslice_max_row() { return kDCAP - kDN + 1; }
+int spmv_xslice_max_row() { return kDCAP; }
 
 hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStream_t s) {
     for (const auto& q : p.xs)
@@ -570,8 +605,49 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
     const int64_t ns = (q.ncols + (1 << swl) - 1) >> swl;
     if (ns > kMaxSlices) return hipErrorInvalidConfiguration;
     const int64_t cost = p.nnz + p.n;
-    const int64_t nb = (cost + kDN - 1) / kDN;
-    if (nb > 0x3fffffff || (int64_t)ns * nb > 0x7ffffffe) return hipErrorInvalidConfiguration;
+    const int64_t nbc = (cost + kDN - 1) / kDN;  // cost blocks
+    if (nbc > 0x3fffffff) return hipErrorInvalidConfiguration;
+    // row blocks: the cost blocks, those above DCAP nonzeros split in two
+    int32_t* rbc = nullptr;
+    int32_t* scnt = nullptr;
+    int32_t* spos = nullptr;
+    int32_t* ssum = nullptr;
+    auto free_split = [&]() {
+        if (rbc) hipFree(rbc);
+        if (scnt) hipFree(scnt);
+        if (spos) hipFree(spos);
+        if (ssum) hipFree(ssum);
+        rbc = scnt = spos = ssum = nullptr;
+    };
+    const int64_t cblk = (nbc + 1023) / 1024;
+    int32_t nb32 = 0;
+    hipError_t es = hipMalloc(&rbc, (size_t)(nbc + 1) * 4);
+    if (es == hipSuccess) es = hipMalloc(&scnt, (size_t)nbc * 4);
+    if (es == hipSuccess) es = hipMalloc(&spos, (size_t)(nbc + 1) * 4);
+    if (es == hipSuccess) es = hipMalloc(&ssum, (size_t)(cblk + 1) * 4);
+    if (es == hipSuccess) {
+        hipLaunchKernelGGL(k_xs_blocks, dim3((unsigned)((nbc + 256) / 256)), dim3(256), 0, s, p.n,
+                           (int)nbc, p.row_ptr, rbc);
+        hipLaunchKernelGGL(k_xs_split_count, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                           (int)nbc, p.row_ptr, rbc, scnt);
+        hipLaunchKernelGGL(k_xs_scan_block, dim3((unsigned)cblk), dim3(1024), 0, s, nbc, scnt,
+                           spos, ssum);
+        hipLaunchKernelGGL(k_xs_scan_top, dim3(1), dim3(1024), 0, s, (int)cblk, ssum, ssum + cblk);
+        hipLaunchKernelGGL(k_xs_scan_add, dim3((unsigned)cblk), dim3(1024), 0, s, nbc, spos, ssum,
+                           ssum + cblk);
+        es = hipGetLastError();
+    }
+    if (es == hipSuccess) es = hipMemcpyAsync(&nb32, spos + nbc, 4, hipMemcpyDeviceToHost, s);
+    if (es == hipSuccess) es = hipStreamSynchronize(s);
+    if (es != hipSuccess) {
+        free_split();
+        return es;
+    }
+    const int64_t nb = nb32;
+    if (nb > 0x3fffffff || (int64_t)ns * nb > 0x7ffffffe) {
+        free_split();
+        return hipErrorInvalidConfiguration;
+    }
     q.ns = (int)ns;
     q.nb = (int)nb;
     const int64_t count = ns * nb;
@@ -583,6 +659,7 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
         if (cnt) hipFree(cnt);
         if (sums) hipFree(sums);
         if (nu) hipFree(nu);
+        free_split();
         q.release();
     };
     hipError_t e = hipMalloc(&q.rb, (size_t)(nb + 1) * 4);
@@ -595,8 +672,8 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
         cleanup();
         return e;
     }
-    hipLaunchKernelGGL(k_xs_blocks, dim3((unsigned)((nb + 256) / 256)), dim3(256), 0, s, p.n,
-                       (int)nb, p.row_ptr, q.rb);
+    hipLaunchKernelGGL(k_xs_split_write, dim3((unsigned)((nbc + 256) / 256)), dim3(256), 0, s,
+                       (int)nbc, p.n, (int)nb, rbc, scnt, spos, q.rb);
     hipLaunchKernelGGL(k_xs_count, dim3((unsigned)nb), dim3(256), 0, s, (int)nb, (int)ns, swl,
                        p.row_ptr, col, q.rb, cnt);
     hipLaunchKernelGGL(k_xs_scan_block, dim3((unsigned)sblk), dim3(1024), 0, s, count, cnt, q.off,
@@ -697,7 +774,7 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
     hipLaunchKernelGGL(k_xs_place, dim3((unsigned)nb), dim3(64), 0, s, (int)nb, (int)ns, swl,
                        p.row_ptr, col, q.rb, q.off, (int64_t)places, q.bcol, q.ej, q.bke);
     hipLaunchKernelGGL(k_xs_units, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p.n,
-                       p.row_ptr, q.unit_ptr, q.rb, (int64_t)units, q.uinfo);
+                       p.row_ptr, q.unit_ptr, q.rb, spos, (int64_t)units, q.uinfo);
     hipLaunchKernelGGL(k_xs_block_info, dim3((unsigned)((nb + 256) / 256)), dim3(256), 0, s,
                        (int)nb, p.row_ptr, q.rb, q.unit_ptr, q.ub, q.kbt);
     e = hipGetLastError();
@@ -705,6 +782,7 @@ hipError_t spmv_prepare_xslice(SpmvPlan& p, int swl, const int32_t* col, hipStre
     hipFree(cnt);
     hipFree(nu);
     cnt = nu = nullptr;
+    free_split();
     if (e != hipSuccess) {
         cleanup();
         return e;

@@ -243,7 +243,7 @@ def test_xslice_values_id(env, orc):
 
 
 def test_xslice_refuses_rows_above_its_limit(env, orc):
-    # a row of 5000 nonzeros is above the family's 4097 limit: its variant
+    # a row of 5000 nonzeros is above the family's 4608 limit: its variant
     # fails to launch and is masked, the others still run
     ao, torch, dev, st = env
     lens = np.full(300, 3, dtype=np.int64)
