@@ -918,7 +918,12 @@ def main():
     collect_s = evaluate.collect_training(region, bufs, N_TRAIN, 4, SIZES[-1], stream, V)
     table_ho, feats_ho, table_ho_s = evaluate.held_out_table(region, bufs, N_HELD_OUT, 40,
                                                              SIZES[-1], 1, 5, stream, V)
-    judged = evaluate.judge(region, table_ho, feats_ho, epochs=200)
+    # 400 epochs: the largest grids sit in the sparse corner of the training
+    # shapes (few shapes have all three extents near 512), where the three-
+    # and four-sweep marches cross over; longer training fits that corner
+    # more reliably (the model's choice at 512^3 otherwise flips between
+    # runs)
+    judged = evaluate.judge(region, table_ho, feats_ho, epochs=400)
     del bufs
     torch.cuda.empty_cache()
     _log(f"selector: {N_TRAIN} training shapes in {collect_s:.0f} s, {N_HELD_OUT} held-out "
