@@ -8,19 +8,21 @@
 // and one per row), a block whose last row would carry it past SPEC = 4096
 // nonzeros being split before that row (so a block holds at most 4096
 // nonzeros, or a single row of at most DCAP = 4608; longer rows are
-// refused).  A per-matrix plan orders
-// the nonzeros slice by slice (slice outer, then block, then CSR order) and
-// keeps, per place, the column inside its slice and the position inside its
-// block (16 bits each).  One execution:
+// refused).  A per-matrix plan orders the nonzeros slice by slice (slice
+// outer, then block, then CSR order) and keeps, per place, the column
+// inside its slice, and per element slot of a block (a fixed stride of
+// DCAP slots) the element's place and its position inside the block.  One
+// execution:
 //
 //   permute   (only when the values changed) the values into that order;
 //   products  one workgroup per chunk of a slice loads the slice of x into
 //             LDS and forms fl(val * x[col]) for its places, streaming;
-//   reduce    one workgroup per row block scatters the block's products from
-//             their slice pieces into LDS at their CSR positions, sums every
-//             row-aligned 64-leaf unit by the canonical tree (one thread per
-//             unit), then combines the unit sums of longer rows by the same
-//             tree, and stores y (or the relaxation update).
+//   reduce    one 512-thread workgroup per row block (four per CU) scatters
+//             the block's products from their slice pieces into LDS at
+//             their CSR positions, sums every row-aligned 64-leaf unit by
+//             the canonical tree (one thread per unit), then combines the
+//             unit sums of longer rows by the same tree, and stores y (or
+//             the relaxation update).
 //
 // The products are the same rounded products and the tree is the same
 // aligned pairwise tree (absent leaves as -0.0, the exact additive
