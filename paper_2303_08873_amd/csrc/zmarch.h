@@ -109,6 +109,43 @@ __device__ __forceinline__ void tb_level(const double* below, const double* cent
                                                k1, plane, lane, i, xin, lane_out, hold);
 }
 
+// Level 1 at plane k with every lane's x-neighbours supplied by nbr(q, xm,
+// xp) for its row q (the staged march reads them from the plane's staged
+// rows in LDS: no cross-lane moves).  Neighbours outside the grid must come
+// as 0 wherever the centre point lies inside; where the centre point or its
+// plane lies outside, the value is zeroed here as in tb_level, so what nbr
+// returns there does not matter.  T >= 2 (level 1 is not the stored one).
+template <int T, int R, bool INNER, typename Nbr>
+__device__ __forceinline__ void tb_level1_nbr(const double* below, const double* centre,
+                                              double* fresh, Nbr nbr, int k, int j0, int ny,
+                                              int nz, bool xin) {
+    static_assert(T >= 2, "level 1 is an intermediate level");
+    using S = TbShape<T, R>;
+    const bool pin = k >= 0 && k < nz;
+    const int jl = j0 - (T - 1);
+#pragma unroll
+    for (int q = 0; q < S::nl(1); ++q) {
+        const int j = jl + q;
+        double xm, xp;
+        nbr(q, xm, xp);
+        double v = xm + xp;
+        v = v + centre[S::off(0) + q];
+        v = v + centre[S::off(0) + q + 2];
+        v = v + below[S::offm(0) + q];
+        v = v + fresh[S::off(0) + q + 1];
+        if constexpr (INNER)
+            fresh[S::off(1) + q] = v * kSixth;
+        else
+            fresh[S::off(1) + q] = (pin && xin && j >= 0 && j < ny) ? v * kSixth : 0.0;
+    }
+    if constexpr (INNER) {
+        if (!pin) {  // wave-uniform: the plane lies outside the grid
+#pragma unroll
+            for (int q = 0; q < S::nl(1); ++q) fresh[S::off(1) + q] = 0.0;
+        }
+    }
+}
+
 // Shift every level by one plane: below <- centre (centre rows of the next
 // level), centre <- fresh.
 template <int T, int R, int L, int STOP = T - 1>
@@ -254,13 +291,20 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         // (boundary waves) are copied from clamped coordinates -- with x0
         // even a piece never straddles x = 0, nor x = nx-1 when nx is even
         // -- and the values read back are zeroed where the point lies
-        // outside; planes outside the grid are zeroed whole.  The
-        // copies are inline assembly with their waits written out: at the
-        // top of each iteration vmcnt(0) covers the copy of plane k+1 issued
-        // in the previous iteration and the stores issued just before it
-        // (level T is stored one iteration late, ahead of the copy, so the
-        // copy is always the youngest memory operation); lgkmcnt(0) before a
-        // buffer is refilled drains the reads of its previous plane; a last
+        // outside; planes outside the grid are zeroed whole.  With four
+        // fused sweeps level 1 takes every lane's x-neighbours straight from
+        // plane k's staged rows (one two-address LDS read per row, no
+        // cross-lane moves; 72 fewer VALU instructions per plane), so plane
+        // k's buffer is refilled with plane k+2 only after level 1; with
+        // fewer sweeps level 1 uses the cross-lane moves and the strip
+        // edges read up front (the LDS form costs those marches a wave per
+        // SIMD) and the buffer is refilled before level 1.  The copies are
+        // inline assembly with their waits written out: at the top of each
+        // iteration vmcnt(0) covers the copy of plane k+1 issued in the
+        // previous iteration and the stores issued before it (level T is
+        // stored one iteration late, ahead of the copy, so the copy is
+        // always the youngest memory operation); lgkmcnt(0) before a buffer
+        // is refilled drains the reads of its previous plane; a last
         // vmcnt(0) leaves no copy writing LDS when the wave ends.
         constexpr int kRowB = 68 * 8;                // one staged row
         constexpr int kPieces = S::nl(0) * 34;       // 16-byte pieces per plane
@@ -296,11 +340,15 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
                              : "s"(m0 + (unsigned)(p * 1024)), "v"((const void*)(pb + poff[p]))
                              : "memory", "m0");
         };
-        // lane's x offset in a staged row: its own point, or (strip edges)
-        // x = i0-1 on lane 0 and x = i0+64 on lane 63
+        // lane's x offset in a staged row (its neighbours at -8 and +8
+        // bytes: columns 1 .. 67 of the 68), and (fewer than four sweeps)
+        // the strip edges x = i0-1 on lane 0 and x = i0+64 on lane 63
+        static_assert(T >= 2, "the staged march fuses at least two sweeps");
+        constexpr bool kNbrLds = T >= 4;
         const int sh = i0 - x0;  // 2 or 3
         const int xo = (lane + sh) * 8;
         const int eo = lane == 0 ? (sh - 1) * 8 : lane == 63 ? (64 + sh) * 8 : xo;
+        const bool xm_ok = i - 1 >= 0 && i - 1 < nx, xp_ok = i + 1 >= 0 && i + 1 < nx;
         auto rd = [&](int kp, int q, int off) -> double {
             return *(const double*)(mine + (kp & 1) * kBuf + q * kRowB + off);
         };
@@ -319,7 +367,6 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
         stage(ka + 1);
         for (int k = ka; k <= kend; ++k) {
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            double ex[S::nl(1)];
 #pragma unroll
             for (int q = 0; q < S::nl(0); ++q) {
                 const double v = rd(k + 1, q, xo);
@@ -330,23 +377,42 @@ __device__ __forceinline__ void tb_column(const double* __restrict__ src, double
                     fresh[q] = (xin && j >= 0 && j < ny) ? v : 0.0;
                 }
             }
-#pragma unroll
-            for (int q = 0; q < S::nl(1); ++q) {
-                const double v = rd(k, q + 1, eo);
-                if constexpr (INNER) {
-                    ex[q] = v;
-                } else {
-                    const int j = j0 - (T - 1) + q;
-                    ex[q] = (eok && j >= 0 && j < ny) ? v : 0.0;
-                }
-            }
             zero_out(k + 1, fresh, S::nl(0));
-            zero_out(k, ex, S::nl(1));
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            store_hold();
-            if (k < kend) stage(k + 2);  // wave-uniform; refills plane k's buffer
-            tb_level<T, R, 1, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz, k0,
-                                            k1, plane, lane, i, xin, lane_out, hold);
+            if constexpr (kNbrLds) {
+                store_hold();
+                // level 1's row q is level 0's row q + 1 of plane k
+                auto nbr = [&](int q, double& xm, double& xp) {
+                    xm = rd(k, q + 1, xo - 8);
+                    xp = rd(k, q + 1, xo + 8);
+                    if constexpr (!INNER) {
+                        xm = xm_ok ? xm : 0.0;
+                        xp = xp_ok ? xp : 0.0;
+                    }
+                };
+                tb_level1_nbr<T, R, INNER>(below, centre, fresh, nbr, k, j0, ny, nz, xin);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // plane k's reads are done
+                if (k < kend) stage(k + 2);  // wave-uniform; refills plane k's buffer
+                tb_level<T, R, 2, NT, T, INNER>(below, centre, fresh, nullptr, dst, k, j0, nx, ny,
+                                                nz, k0, k1, plane, lane, i, xin, lane_out, hold);
+            } else {
+                double ex[S::nl(1)];
+#pragma unroll
+                for (int q = 0; q < S::nl(1); ++q) {
+                    const double v = rd(k, q + 1, eo);
+                    if constexpr (INNER) {
+                        ex[q] = v;
+                    } else {
+                        const int j = j0 - (T - 1) + q;
+                        ex[q] = (eok && j >= 0 && j < ny) ? v : 0.0;
+                    }
+                }
+                zero_out(k, ex, S::nl(1));
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // plane k's reads are done
+                store_hold();
+                if (k < kend) stage(k + 2);  // wave-uniform; refills plane k's buffer
+                tb_level<T, R, 1, NT, T, INNER>(below, centre, fresh, ex, dst, k, j0, nx, ny, nz,
+                                                k0, k1, plane, lane, i, xin, lane_out, hold);
+            }
             hold_p = k - T + 1;
             tb_rotate<T, R, 0>(below, centre, fresh);
         }

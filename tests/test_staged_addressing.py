@@ -7,10 +7,11 @@ whole launches, including 74-plane z-chunks and boundary waves:
 
 * every 16-byte global->LDS piece reads inside the grid (clamped
   coordinates) and lands inside its wave's buffer;
-* every level-0 value and strip-edge value the march reads back from LDS
-  comes from the intended grid point whenever that point lies inside the
-  grid (points outside are zeroed by the kernel, so any clamped piece there
-  is harmless);
+* every level-0 value, and every x-neighbour level 1 takes (four sweeps)
+  or strip-edge value (fewer), that the march reads back from LDS comes
+  from the intended grid point whenever that point lies inside the grid
+  (points outside are zeroed by the kernel, so any clamped piece there is
+  harmless);
 * a plane buffer is refilled only after the plane it held has been read
   (two buffers, plane kp in buffer kp & 1, refill of plane k+2 after the
   reads of iteration k);
@@ -82,7 +83,8 @@ def check_wave(T, R, nx, ny, nz, i0, j0, k0, k1):
         assert lds_map[byte] == (j_want, x_want), (kp, q, off, lds_map[byte], (j_want, x_want))
 
     # buffer b holds plane `held[b]`; planes read in iteration k: k+1 (level
-    # 0) and k (edges); refilled after the reads: plane k+2 into (k+2) & 1
+    # 0) and k (level 1's x-neighbours or the strip edges); refilled after
+    # those reads: plane k+2 into (k+2) & 1
     held = {ka & 1: ka, (ka + 1) & 1: ka + 1}
     for k in range(ka, kend + 1):
         assert held[(k + 1) & 1] == k + 1 and held[k & 1] == k
@@ -91,10 +93,17 @@ def check_wave(T, R, nx, ny, nz, i0, j0, k0, k1):
             xo = (lane + sh) * 8
             for q in range(n0):
                 read(k + 1, q, xo, i, j0 - T + q)
-            eo = (sh - 1) * 8 if lane == 0 else (64 + sh) * 8 if lane == 63 else xo
-            ie = i0 - 1 if lane == 0 else i0 + 64 if lane == 63 else i
-            for q in range(nl(T, R, 1)):
-                read(k, q + 1, eo, ie, j0 - (T - 1) + q)
+            if T >= 4:
+                # level 1's x-neighbours: the lane's x-1 and x+1 in plane k's row
+                for q in range(nl(T, R, 1)):
+                    read(k, q + 1, xo - 8, i - 1, j0 - (T - 1) + q)
+                    read(k, q + 1, xo + 8, i + 1, j0 - (T - 1) + q)
+            else:
+                # the strip edges: x = i0-1 on lane 0, x = i0+64 on lane 63
+                eo = (sh - 1) * 8 if lane == 0 else (64 + sh) * 8 if lane == 63 else xo
+                ie = i0 - 1 if lane == 0 else i0 + 64 if lane == 63 else i
+                for q in range(nl(T, R, 1)):
+                    read(k, q + 1, eo, ie, j0 - (T - 1) + q)
         if k < kend:
             held[(k + 2) & 1] = k + 2  # plane k's buffer, read above
 
