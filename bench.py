@@ -299,12 +299,13 @@ def batch_pmc_traffic(chosen):
     return d.get("traffic_bytes_per_replay")
 
 
-def batch_kernel_only(replays: int = 5):
+def batch_kernel_only(replays: int = 5, tiles=None):
     """Counter runs of the batched launch: the 256-grid workload (seed 3, 5
-    sweeps), autotuned, then a marker copy of 1024 doubles, `replays`
-    replays of the captured graph, and 5 copies of 512^3 doubles (the
-    calibration kernel).  The replays are the batch-kernel dispatches after
-    the marker."""
+    sweeps), autotuned (or on the given tile candidate per size bucket, so
+    that separate counter runs profile the same graph), then a marker copy
+    of 1024 doubles, `replays` replays of the captured graph, and 5 copies
+    of 512^3 doubles (the calibration kernel).  The replays are the
+    batch-kernel dispatches after the marker."""
     import torch
 
     import paper_2303_08873_amd as ao
@@ -319,7 +320,11 @@ def batch_kernel_only(replays: int = 5):
         bufs.append((u0, out))
         ins.append(ao.jacobi_args(u0, out, int(nx), int(ny), int(nz), 5))
     b = ao.batch_create(ins)
-    chosen = ao.batch_autotune(b, stream=stream, warmup=1, reps=3)
+    if tiles:
+        ao.batch_set_tiles(b, tiles)
+        chosen = list(tiles)
+    else:
+        chosen = ao.batch_autotune(b, stream=stream, warmup=1, reps=3)
     ao.batch_run(b, stream=stream, use_graph=True)  # capture
     torch.cuda.synchronize()
     mark = torch.zeros(2048, dtype=torch.float64, device=dev)
@@ -854,6 +859,9 @@ def main():
                     help="counter-collection mode: one size-sweep variant at 512^3 only; with "
                          "--workload spmv one SpMV variant on the 2^22 matrix; with --workload "
                          "batch the autotuned graph of the batched workload")
+    ap.add_argument("--tiles", default=None,
+                    help="with --workload batch --kernel-only: five tile candidate ids, one per "
+                         "size bucket, instead of autotuning (comma-separated)")
     ap.add_argument("--trace-steps", action="store_true",
                     help="trace mode: the timed size-sweep loop with fixed variant picks only")
     ap.add_argument("--workload", default="size-sweep",
@@ -867,7 +875,7 @@ def main():
         if args.workload == "spmv":
             spmv_kernel_only(args.kernel_only)
         elif args.workload == "batch":
-            batch_kernel_only()
+            batch_kernel_only(tiles=[int(t) for t in args.tiles.split(",")] if args.tiles else None)
         else:
             kernel_only(args.kernel_only)
         return
