@@ -1,6 +1,6 @@
 """Learned-selector evaluation of the Jacobi region (one GPU).
 
-Training data come from the method itself: a region with the 10 size-sweep
+Training data come from the method itself: a region with the 11 size-sweep
 variants runs every training shape once per variant under RoundRobin
 exploration (Sec. 2 Apollo paragraph), each run profiled.  The cost model
 is trained on those records by the library's GPU kernels.  Held-out shapes
