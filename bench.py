@@ -185,6 +185,25 @@ def pmc_traffic(variant_key):
     return d.get("traffic_bytes_per_launch")
 
 
+SPMV_SOURCES = ("spmv_xslice.hip", "internal.h")
+
+
+def spmv_pmc_traffic(variant_key):
+    """HBM bytes per SpMV of an x-slice variant on the 2^22 matrix (seed 5)
+    from the committed counter summary (FETCH_SIZE + WRITE_SIZE of its
+    products and reduce passes, scaled by the copy-probe calibration), when
+    it was taken for this variant and these kernel sources."""
+    path = os.path.join(ROOT, "profiles", "spmv_xslice_pmc.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != source_digest(SPMV_SOURCES):
+        return None
+    return d.get("variants", {}).get(variant_key, {}).get("traffic_bytes_per_spmv")
+
+
 def copy_probe(ao, torch, dev, stream, n=512 ** 3, reps=20):
     """Achievable HBM bandwidth: the library's plain FP64 copy of n doubles."""
     a = synth_u01(torch, dev, n)
@@ -618,6 +637,8 @@ def spmv_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
     probes = gather_probes(ao, torch, stream, t["col"], t["x"], n)
     gbs = byt / sec / 1e9
     v = variants[best]
+    vkey = f"family={v.family} bx={v.bx} by={v.by}"
+    traffic = spmv_pmc_traffic(vkey)
     res = {"value": round(gbs, 2), "unit": "GB/s",
            "workload": "CSR SpMV n=2^22, Pareto rows tail 1.5 mean 16 max 4096, seed 5",
            "nnz": nnz, "algorithmic_bytes": byt, "us_per_spmv": round(sec * 1e6, 2),
@@ -630,9 +651,11 @@ def spmv_measure(steps: int, warmup: int, no_cpu_baseline: bool = False):
                                                      for k, v in xs_fresh.items()},
            "variants": [f"family={x.family} bx={x.bx} by={x.by}" for x in variants],
            "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": f"variant {best} (family={v.family} bx={v.bx} by={v.by}) "
-                                  f"at n=2^22"}}
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": traffic,
+                        "traffic_frac": (round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+                                         if traffic else None),
+                        "kernel": f"variant {best} ({vkey}) at n=2^22"}}
     if not no_cpu_baseline:
         import oracle
         res["cpu_baseline"] = oracle_timing(
@@ -822,11 +845,15 @@ def cosched_workload(steps: int, warmup: int):
     print(json.dumps(res), flush=True)
 
 
+SPMV_COPY_DOUBLES = 1 << 27
+
+
 def spmv_kernel_only(variant: int, launches: int = 5):
     """Counter runs: SpMV variant `variant` on the 2^22 matrix, `launches`
-    executions.  Ids 0..8 are {thread-row, wave-row, merge-path} x {64, 256,
-    1024}; 9 and 10 the x-slice family with 8K- and 16K-column slices (the
-    values reordered once: the matrix keeps one values id)."""
+    executions, then 5 copies of 2^27 doubles (the calibration kernel of
+    known traffic).  Ids 0..8 are {thread-row, wave-row, merge-path} x {64,
+    256, 1024}; 9 and 10 the x-slice family with 8K- and 16K-column slices
+    (the values reordered once: the matrix keeps one values id)."""
     import torch
 
     import paper_2303_08873_amd as ao
@@ -845,8 +872,16 @@ def spmv_kernel_only(variant: int, launches: int = 5):
     for _ in range(launches):
         ao.region_run(region, a, stream=stream, variant=variant)
     torch.cuda.synchronize()
+    del a, t, y
+    ao.region_destroy(region)
+    u = synth_u01(torch, dev, SPMV_COPY_DOUBLES)
+    b = torch.empty_like(u)
+    for _ in range(5):
+        ao.ao_hbm_copy(u, b, SPMV_COPY_DOUBLES, stream=stream)
+    torch.cuda.synchronize()
     print(json.dumps({"spmv_kernel_only": variant, "launches": launches,
-                      "nnz": int(m["col"].size)}), flush=True)
+                      "nnz": int(m["col"].size), "copies": 5,
+                      "copy_bytes_each": 16 * SPMV_COPY_DOUBLES}), flush=True)
 
 
 def main():
