@@ -145,6 +145,14 @@ enum ao_family {
                                  (four sweeps) or 6 (three) only waves inside the grid,
                                  and for odd nx only waves whose 68 staged columns lie
                                  inside it */
+#define AO_VF_FILL_Z 32       /* register z-marches of one to four sweeps: bz is an
+                                 upper bound; each launch takes the planes per block,
+                                 at most bz, that give the fewest plane steps on the
+                                 busiest workgroup slot of the device (the grid's
+                                 blocks in rounds of the workgroups the kernel keeps
+                                 resident, each block marching its planes plus the
+                                 2(T-1) halo planes of T fused sweeps; ties to the
+                                 longer chunk), so mid-size grids fill the chip */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,
@@ -452,6 +460,18 @@ int ao_gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, 
 
 /* Number of compute units of the current device (0 if none). */
 int ao_device_cus(void);
+
+/* Planes per block that one launch of GPU Jacobi variant *v (a register
+ * z-march family: ZREG, ZREG_T2, ZREG_T3, ZREG_T4) uses on an nx x ny x nz
+ * grid: v->bz, or with AO_VF_FILL_Z the chunk length chosen for `resident`
+ * workgroups on the device at once (resident <= 0: the kernel's own
+ * occupancy on the current device times its CU count; then a device must be
+ * present).  Written to *planes; AO_EINVAL for non-positive dimensions, a
+ * null pointer or a variant that fits no z-march kernel.  Reports the launch
+ * geometry a profiled variant actually ran (Sec. 3.1: a variant is its
+ * launch configuration). */
+int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int64_t resident,
+                     int32_t* planes);
 
 #ifdef __cplusplus
 }

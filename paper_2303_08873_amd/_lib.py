@@ -24,6 +24,7 @@ AO_VF_HALO_PREFETCH = 2
 AO_VF_OCCUPANCY = 4
 AO_VF_STAGED = 8
 AO_VF_LDS_SWEEPS = 16
+AO_VF_FILL_Z = 32
 AO_PROFILE_RECORD = 1
 
 _STATUS = {-1: "AO_EINVAL", -2: "AO_ENOMEM", -3: "AO_EHIP", -4: "AO_ESTATE", -5: "AO_EEXIST",
@@ -113,6 +114,7 @@ def _load():
         "region_clear_memo": [P],
         "region_destroy": [P],
         "ao_device_cus": [],
+        "ao_jacobi_planes": [P, I, I, I, ctypes.c_int64, P],
         "ao_hbm_copy": [P, P, ctypes.c_int64, I, P],
         "ao_gather_probe": [P, P, ctypes.c_int64, ctypes.c_int64, P, P],
     }
@@ -277,6 +279,14 @@ def ao_gather_probe(idx, x, m: int, nx: int, out, stream=None) -> None:
 
 def ao_device_cus() -> int:
     return lib.ao_device_cus()
+
+
+def ao_jacobi_planes(variant: Variant, nx: int, ny: int, nz: int, resident: int = 0) -> int:
+    """Planes per block one launch of a register z-march variant uses on an
+    nx x ny x nz grid (for `resident` workgroups at once; 0: the device's)."""
+    out = ctypes.c_int32()
+    _check(lib.ao_jacobi_planes(ctypes.byref(variant), nx, ny, nz, resident, ctypes.byref(out)))
+    return out.value
 
 
 def batch_create(instances):

@@ -27,6 +27,19 @@ hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, doubl
 // Three or four sweeps at once (families ZREG_T3 / ZREG_T4): dst <- J^T(src).
 hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double* dst, int nx,
                                  int ny, int nz, hipStream_t s);
+// Planes per block of a launch of a register z-march variant (v.bz, or with
+// AO_VF_FILL_Z the chunk fill_planes picks) on an nx * ny * nz grid, for
+// `resident` workgroups at once (<= 0: the kernel's residency on the
+// current device); hipErrorInvalidConfiguration for a variant that fits no
+// z-march kernel.
+hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int64_t resident,
+                             int* planes);
+// The chunk length, at most bz_max planes, that minimises the plane steps of
+// the busiest workgroup slot when `columns` columns of blocks are cut into
+// z-chunks: the blocks run in ceil(blocks / resident) rounds, each marching
+// its chunk plus `halo` planes (2(T-1) for T fused sweeps); ties go to the
+// longer chunk (less halo traffic).
+int fill_planes(int64_t columns, int nz, int bz_max, int halo, int64_t resident);
 // All `sweeps` sweeps dst <- J^sweeps(src) of a grid of at most 8192 points
 // in one launch of one workgroup (the grid held twice in LDS);
 // hipErrorInvalidConfiguration for a larger grid.

@@ -33,6 +33,11 @@
 // All map blockIdx.x to tiles XCD-aware: the hardware deals workgroups to
 // the 8 XCDs round-robin, so consecutive logical tiles (which share z- and
 // y-neighbour planes) are remapped to the same XCD and meet in its L2.
+#include <algorithm>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "internal.h"
 #include "lanes.h"
 #include "zmarch.h"
@@ -524,68 +529,139 @@ __global__ __launch_bounds__(64 * kZregWaves) void jac_zreg_tb(const double* __r
     zreg_tb_body<T, R, NT, PF, ST>(src, dst, nx, ny, nz, nbx, nby, bz, nblocks);
 }
 
+// Every register z-march kernel takes (src, dst, nx, ny, nz, nbx, nby, bz,
+// blocks) and runs 4-wave workgroups over nbx * nby columns of blocks times
+// ceil(nz / bz) z-chunks.
+using ColumnKernel = void (*)(const double*, double*, int, int, int, int, int, int, unsigned);
+
 template <int T, int R>
-hipError_t launch_zreg_tb(bool nt, bool pf, bool st, dim3 grid, hipStream_t s, const double* src,
-                          double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
-                          unsigned nb) {
-    const dim3 block(64 * kZregWaves);
-    if (st && nt)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false, true>), grid, block, 0, s, src, dst, nx,
-                           ny, nz, nbx, nby, bz, nb);
-    else if (st)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false, true>), grid, block, 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
-    else if (nt && pf)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, true, false>), grid, block, 0, s, src, dst, nx,
-                           ny, nz, nbx, nby, bz, nb);
-    else if (nt)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, true, false, false>), grid, block, 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
-    else if (pf)
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, true, false>), grid, block, 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
-    else
-        hipLaunchKernelGGL((jac_zreg_tb<T, R, false, false, false>), grid, block, 0, s, src, dst,
-                           nx, ny, nz, nbx, nby, bz, nb);
-    return hipGetLastError();
+ColumnKernel pick_zreg_tb(bool nt, bool pf, bool st) {
+    if (st && nt) return jac_zreg_tb<T, R, true, false, true>;
+    if (st) return jac_zreg_tb<T, R, false, false, true>;
+    if (nt && pf) return jac_zreg_tb<T, R, true, true, false>;
+    if (nt) return jac_zreg_tb<T, R, true, false, false>;
+    if (pf) return jac_zreg_tb<T, R, false, true, false>;
+    return jac_zreg_tb<T, R, false, false, false>;
 }
 
 template <int R, bool PF>
-hipError_t launch_zreg_t2(bool nt, bool occ, dim3 grid, hipStream_t s, const double* src,
-                          double* dst, int nx, int ny, int nz, int nbx, int nby, int bz,
-                          unsigned nb) {
-    const dim3 block(64 * kZregWaves);
-    if (occ && nt)
-        hipLaunchKernelGGL((jac_zreg_t2_occ<R, true, PF>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
-    else if (occ)
-        hipLaunchKernelGGL((jac_zreg_t2_occ<R, false, PF>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
-    else if (nt)
-        hipLaunchKernelGGL((jac_zreg_t2<R, true, PF>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
-    else
-        hipLaunchKernelGGL((jac_zreg_t2<R, false, PF>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
-    return hipGetLastError();
+ColumnKernel pick_zreg_t2(bool nt, bool occ) {
+    if (occ && nt) return jac_zreg_t2_occ<R, true, PF>;
+    if (occ) return jac_zreg_t2_occ<R, false, PF>;
+    if (nt) return jac_zreg_t2<R, true, PF>;
+    return jac_zreg_t2<R, false, PF>;
 }
 
 template <int R, int VX>
-hipError_t launch_zreg(bool nt, bool pf, dim3 grid, hipStream_t s, const double* src, double* dst,
-                       int nx, int ny, int nz, int nbx, int nby, int bz, unsigned nb) {
-    const dim3 block(64 * kZregWaves);
-    if (nt && pf)
-        hipLaunchKernelGGL((jac_zreg<R, VX, true, true>), grid, block, 0, s, src, dst, nx, ny, nz,
-                           nbx, nby, bz, nb);
-    else if (nt)
-        hipLaunchKernelGGL((jac_zreg<R, VX, true, false>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
-    else if (pf)
-        hipLaunchKernelGGL((jac_zreg<R, VX, false, true>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
-    else
-        hipLaunchKernelGGL((jac_zreg<R, VX, false, false>), grid, block, 0, s, src, dst, nx, ny,
-                           nz, nbx, nby, bz, nb);
+ColumnKernel pick_zreg(bool nt, bool pf) {
+    if (nt && pf) return jac_zreg<R, VX, true, true>;
+    if (nt) return jac_zreg<R, VX, true, false>;
+    if (pf) return jac_zreg<R, VX, false, true>;
+    return jac_zreg<R, VX, false, false>;
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Workgroups of kernel k the current device keeps resident at once (its
+// occupancy per CU times the CU count), cached per kernel and device; 0
+// when the runtime cannot say.
+int64_t resident_blocks(ColumnKernel k) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void*, int>, int64_t>> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const std::pair<const void*, int> key((const void*)k, dev);
+    std::lock_guard<std::mutex> g(mu);
+    for (const auto& e : cache)
+        if (e.first == key) return e.second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * kZregWaves, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int64_t r = (int64_t)std::max(per_cu, 0) * std::max(cus, 0);
+    cache.push_back({key, r});
+    return r;
+}
+
+// What a full launch of a register z-march variant runs: its kernel, the
+// sweeps it fuses and its nbx * nby columns of blocks.
+struct ColumnShape {
+    ColumnKernel k = nullptr;
+    int T = 1, nbx = 0, nby = 0;
+};
+
+// The shape of variant v on an nx * ny * nz grid (all positive), after the
+// host-side checks of its family; hipErrorInvalidConfiguration when the
+// variant does not fit a kernel.
+hipError_t column_shape(const ao_variant& v, int nx, int ny, int nz, ColumnShape* c) {
+    const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
+    const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
+    const int R = v.by;
+    if (v.bz <= 0 || nz <= 0) return hipErrorInvalidConfiguration;
+    if (v.family == AO_FAM_JACOBI_ZREG) {
+        // strips of bx = 64 or 128 points (128: an even nx), by rows per wave
+        const int VX = v.bx / 64;
+        if (v.bx != 64 && v.bx != 128) return hipErrorInvalidConfiguration;
+        if (VX == 2 && (nx & 1)) return hipErrorInvalidConfiguration;
+#define AO_ZREG(RR, VV) \
+    if (R == RR && VX == VV) c->k = pick_zreg<RR, VV>(nt, pf);
+        AO_ZREG(1, 1) AO_ZREG(2, 1) AO_ZREG(4, 1) AO_ZREG(8, 1)
+        AO_ZREG(1, 2) AO_ZREG(2, 2) AO_ZREG(4, 2) AO_ZREG(8, 2)
+#undef AO_ZREG
+        c->T = 1;
+        c->nbx = cdiv(nx, v.bx);
+    } else if (v.family == AO_FAM_JACOBI_ZREG_T2) {
+        const bool occ = (v.flags & AO_VF_OCCUPANCY) != 0;
+        if (v.bx != 64 || nx > (1 << 28)) return hipErrorInvalidConfiguration;
+#define AO_T2(RR) \
+    if (R == RR) c->k = pf ? pick_zreg_t2<RR, true>(nt, occ) : pick_zreg_t2<RR, false>(nt, occ);
+        AO_T2(1) AO_T2(2) AO_T2(3) AO_T2(4) AO_T2(6) AO_T2(8) AO_T2(10) AO_T2(12) AO_T2(16)
+#undef AO_T2
+        c->T = 2;
+        c->nbx = cdiv(nx, 62);
+    } else if (v.family == AO_FAM_JACOBI_ZREG_T3 || v.family == AO_FAM_JACOBI_ZREG_T4) {
+        const int T = v.family == AO_FAM_JACOBI_ZREG_T3 ? 3 : 4;
+        const bool st = (v.flags & AO_VF_STAGED) != 0;
+        if (v.bx != 64 || nx > (1 << 28) || (st && pf)) return hipErrorInvalidConfiguration;
+#define AO_TB(TT, RR) \
+    if (T == TT && R == RR) c->k = pick_zreg_tb<TT, RR>(nt, pf, st);
+        AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 5) AO_TB(3, 6) AO_TB(3, 8)
+        AO_TB(4, 1) AO_TB(4, 2) AO_TB(4, 3) AO_TB(4, 4) AO_TB(4, 5)
+#undef AO_TB
+        c->T = T;
+        c->nbx = cdiv(nx, 66 - 2 * T);
+    }
+    if (!c->k) return hipErrorInvalidConfiguration;
+    c->nby = cdiv(ny, kZregWaves * R);
+    return hipSuccess;
+}
+
+// Planes per block of a launch of shape c for variant v: v.bz, or with
+// AO_VF_FILL_Z the chunk fill_planes picks for `resident` workgroups (the
+// kernel's own residency on the current device when resident <= 0).
+int column_planes(const ao_variant& v, const ColumnShape& c, int nz, int64_t resident) {
+    if (!(v.flags & AO_VF_FILL_Z)) return v.bz;
+    if (resident <= 0) resident = resident_blocks(c.k);
+    return fill_planes((int64_t)c.nbx * c.nby, nz, v.bz, 2 * (c.T - 1), resident);
+}
+
+// One launch of a register z-march variant: src -> dst.
+hipError_t launch_columns(const ao_variant& v, hipStream_t s, const double* src, double* dst,
+                          int nx, int ny, int nz) {
+    ColumnShape c;
+    const hipError_t e = column_shape(v, nx, ny, nz, &c);
+    if (e != hipSuccess) return e;
+    const int bz = column_planes(v, c, nz, 0);
+    const int64_t nb = (int64_t)c.nbx * c.nby * ((nz + bz - 1) / bz);
+    if (bz <= 0 || nb > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(c.k, dim3((unsigned)nb), dim3(64 * kZregWaves), 0, s, src, dst, nx, ny, nz,
+                       c.nbx, c.nby, bz, (unsigned)nb);
     return hipGetLastError();
 }
 
@@ -609,9 +685,23 @@ __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src,
     }
 }
 
-inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-
 }  // namespace
+
+int fill_planes(int64_t columns, int nz, int bz_max, int halo, int64_t resident) {
+    const int top = std::min(bz_max, nz);
+    if (top < 1 || columns < 1 || resident < 1) return std::max(top, 1);
+    int best = top;
+    int64_t best_cost = INT64_MAX;
+    for (int bz = top; bz >= std::max(1, top - 4095); --bz) {
+        const int64_t blocks = columns * ((nz + bz - 1) / bz);
+        const int64_t cost = ((blocks + resident - 1) / resident) * (bz + halo);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = bz;
+        }
+    }
+    return best;
+}
 
 bool lds_sweeps_fit(int nx, int ny, int nz) {
     return nx > 0 && ny > 0 && nz > 0 && (int64_t)nx * ny * nz <= kLdsPoints;
@@ -662,24 +752,10 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
         return hipGetLastError();
     }
     if (v.family == AO_FAM_JACOBI_ZREG) {
-        // bx = strip width (64 or 128 points), by = rows per wave, bz = planes
-        const int VX = bx / 64, R = by, bz = v.bz;
-        const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
-        if ((bx != 64 && bx != 128) || bz <= 0) return hipErrorInvalidConfiguration;
-        if (VX == 2 && ((nx & 1) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)))
+        // a 128-point strip takes 16-byte accesses
+        if (bx == 128 && (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)))
             return hipErrorInvalidConfiguration;
-        const int nbxz = cdiv(nx, bx), nbyz = cdiv(ny, kZregWaves * R);
-        const int64_t nb = (int64_t)nbxz * nbyz * cdiv(nz, bz);
-        if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
-        const dim3 grid((unsigned)nb);
-        const unsigned u = (unsigned)nb;
-#define AO_ZREG(RR, VV)                                                                  \
-    if (R == RR && VX == VV)                                                             \
-        return launch_zreg<RR, VV>(nt, pf, grid, s, src, dst, nx, ny, nz, nbxz, nbyz, bz, u);
-        AO_ZREG(1, 1) AO_ZREG(2, 1) AO_ZREG(4, 1) AO_ZREG(8, 1)
-        AO_ZREG(1, 2) AO_ZREG(2, 2) AO_ZREG(4, 2) AO_ZREG(8, 2)
-#undef AO_ZREG
-        return hipErrorInvalidConfiguration;
+        return launch_columns(v, s, src, dst, nx, ny, nz);
     }
     return hipErrorInvalidValue;
 }
@@ -687,50 +763,26 @@ hipError_t jacobi_gpu_sweep(const ao_variant& v, const double* src, double* dst,
 hipError_t jacobi_gpu_double_sweep(const ao_variant& v, const double* src, double* dst, int nx,
                                   int ny, int nz, hipStream_t s) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
-    const int R = v.by, bz = v.bz;
-    if (v.family != AO_FAM_JACOBI_ZREG_T2 || v.bx != 64 || bz <= 0 || nx > (1 << 28))
-        return hipErrorInvalidConfiguration;
-    const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
-    const bool occ = (v.flags & AO_VF_OCCUPANCY) != 0;
-    const int nbx = cdiv(nx, 62), nby = cdiv(ny, kZregWaves * R);
-    const int64_t nb = (int64_t)nbx * nby * cdiv(nz, bz);
-    if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nb);
-    const unsigned u = (unsigned)nb;
-    const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
-#define AO_T2(RR)                                                                                \
-    if (R == RR)                                                                                 \
-        return pf ? launch_zreg_t2<RR, true>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, \
-                                             u)                                                  \
-                  : launch_zreg_t2<RR, false>(nt, occ, grid, s, src, dst, nx, ny, nz, nbx, nby,   \
-                                              bz, u);
-    AO_T2(1) AO_T2(2) AO_T2(3) AO_T2(4) AO_T2(6) AO_T2(8) AO_T2(10) AO_T2(12) AO_T2(16)
-#undef AO_T2
-    return hipErrorInvalidConfiguration;
+    if (v.family != AO_FAM_JACOBI_ZREG_T2) return hipErrorInvalidConfiguration;
+    return launch_columns(v, s, src, dst, nx, ny, nz);
 }
 
 hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double* dst, int nx,
                                  int ny, int nz, hipStream_t s) {
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
-    const int R = v.by, bz = v.bz;
-    const int T = v.family == AO_FAM_JACOBI_ZREG_T3 ? 3 : v.family == AO_FAM_JACOBI_ZREG_T4 ? 4 : 0;
-    if (T == 0 || v.bx != 64 || bz <= 0 || nx > (1 << 28)) return hipErrorInvalidConfiguration;
-    const bool nt = (v.flags & AO_VF_NT_STORE) != 0;
-    const bool pf = (v.flags & AO_VF_HALO_PREFETCH) != 0;
-    const bool st = (v.flags & AO_VF_STAGED) != 0;
-    if (st && pf) return hipErrorInvalidConfiguration;
-    const int nbx = cdiv(nx, 66 - 2 * T), nby = cdiv(ny, kZregWaves * R);
-    const int64_t nb = (int64_t)nbx * nby * cdiv(nz, bz);
-    if (nb > 0x7fffffff) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nb);
-    const unsigned u = (unsigned)nb;
-#define AO_TB(TT, RR)                                                                          \
-    if (T == TT && R == RR)                                                                    \
-        return launch_zreg_tb<TT, RR>(nt, pf, st, grid, s, src, dst, nx, ny, nz, nbx, nby, bz, u);
-    AO_TB(3, 1) AO_TB(3, 2) AO_TB(3, 3) AO_TB(3, 4) AO_TB(3, 5) AO_TB(3, 6) AO_TB(3, 8)
-    AO_TB(4, 1) AO_TB(4, 2) AO_TB(4, 3) AO_TB(4, 4) AO_TB(4, 5)
-#undef AO_TB
-    return hipErrorInvalidConfiguration;
+    if (v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4)
+        return hipErrorInvalidConfiguration;
+    return launch_columns(v, s, src, dst, nx, ny, nz);
+}
+
+hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int64_t resident,
+                             int* planes) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !planes) return hipErrorInvalidValue;
+    ColumnShape c;
+    const hipError_t e = column_shape(v, nx, ny, nz, &c);
+    if (e != hipSuccess) return e;
+    *planes = column_planes(v, c, nz, resident);
+    return hipSuccess;
 }
 
 hipError_t hbm_copy(const double* src, double* dst, int64_t n, bool nt, hipStream_t s) {

@@ -191,6 +191,11 @@ int validate_variant(int kind, const ao_variant& v, int id) {
         if ((v.flags & AO_VF_LDS_SWEEPS) && v.family != AO_FAM_JACOBI_DIRECT)
             return fail(AO_EINVAL, at + "all sweeps in LDS is a flag of the one-point-per-thread "
                                         "family");
+        if ((v.flags & AO_VF_FILL_Z) &&
+            (v.family != AO_FAM_JACOBI_ZREG && v.family != AO_FAM_JACOBI_ZREG_T2 &&
+             v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4))
+            return fail(AO_EINVAL, at + "filling the device by z-chunk length is for the "
+                                        "register z-marches");
         if ((v.flags & AO_VF_STAGED) &&
             ((v.family != AO_FAM_JACOBI_ZREG_T3 && v.family != AO_FAM_JACOBI_ZREG_T4) ||
              (v.flags & AO_VF_HALO_PREFETCH)))
@@ -554,20 +559,20 @@ hipError_t jacobi_launch(const ao_variant& v, const JacobiPlan& p, int l, const 
         if (p.rem == 1) {
             const int rows = v.by >= 8 ? 8 : v.by >= 4 ? 4 : v.by >= 2 ? 2 : 1;
             const ao_variant one{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG, 64, rows, v.bz,
-                                 v.flags & AO_VF_NT_STORE};
+                                 v.flags & (AO_VF_NT_STORE | AO_VF_FILL_Z)};
             return jacobi_gpu_sweep(one, src, dst, nx, ny, nz, s);
         }
         if (p.rem == 2) {
             int rows = v.by;
             while (rows > 1 && !t2_rows_ok(rows)) --rows;
             const ao_variant two{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T2, 64, rows, v.bz,
-                                 v.flags & AO_VF_NT_STORE};
+                                 v.flags & (AO_VF_NT_STORE | AO_VF_FILL_Z)};
             return jacobi_gpu_double_sweep(two, src, dst, nx, ny, nz, s);
         }
         int rows = v.by;
         while (rows > 1 && !t3_rows_ok(rows)) --rows;
         const ao_variant three{AO_TARGET_GPU, AO_FAM_JACOBI_ZREG_T3, 64, rows, v.bz,
-                               v.flags & AO_VF_NT_STORE};
+                               v.flags & (AO_VF_NT_STORE | AO_VF_FILL_Z)};
         return jacobi_gpu_multi_sweep(three, src, dst, nx, ny, nz, s);
     }
     return p.P == 2 ? jacobi_gpu_double_sweep(v, src, dst, nx, ny, nz, s)
@@ -1301,6 +1306,20 @@ int ao_gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, 
         (void)hipGetLastError();
         return fail(AO_EHIP, hip_msg("gather probe", e));
     }
+    return AO_OK;
+}
+
+int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int64_t resident,
+                     int32_t* planes) {
+    if (!v || !planes || nx <= 0 || ny <= 0 || nz <= 0 || v->target != AO_TARGET_GPU)
+        return fail(AO_EINVAL, "bad arguments");
+    int p = 0;
+    const hipError_t e = jacobi_gpu_planes(*v, nx, ny, nz, resident, &p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AO_EINVAL, "not a register z-march variant that fits its kernels");
+    }
+    *planes = p;
     return AO_OK;
 }
 

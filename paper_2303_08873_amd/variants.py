@@ -3,7 +3,8 @@ as categorical variants are numbered from 0 in the order given, Sec. 3.1
 model_output clause)."""
 from __future__ import annotations
 
-from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_LDS_SWEEPS, AO_VF_NT_STORE, AO_VF_STAGED,
+from ._lib import (AO_TARGET_GPU, AO_TARGET_HOST, AO_VF_FILL_Z, AO_VF_LDS_SWEEPS, AO_VF_NT_STORE,
+                   AO_VF_STAGED,
                    FAM_JACOBI_DIRECT, FAM_JACOBI_HOST, FAM_JACOBI_ZREG_T3,
                    FAM_JACOBI_ZREG_T4, FAM_SPMV_XSLICE,
                    FAM_SPMV_MERGE_PATH, FAM_SPMV_THREAD_ROW, FAM_SPMV_WAVE_ROW, Variant)
@@ -19,8 +20,8 @@ def jacobi_variants_blocks():
 
 # ids 0..5 run on the GPU, 6..10 on the host CPU (device-selection use case)
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_ZREG_T3, 64, 1, 1, AO_VF_STAGED), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
-                    (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED),
-                    (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED | AO_VF_FILL_Z),
+                    (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED | AO_VF_FILL_Z),
                     (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED),
                     (FAM_JACOBI_DIRECT, 64, 16, 1, AO_VF_LDS_SWEEPS)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
@@ -31,8 +32,8 @@ def jacobi_variants_sweep():
     """11 variants: 6 GPU kernels (the three-sweep register z-march with
     level 0 staged, 1 row per wave and 1 plane per block for small grids;
     one point per thread with 64x4 threads, the static default; three- and
-    four-sweep marches with 4 rows per wave and 22, 74 or 4 planes per
-    block; one point per thread with 64x16 threads and small grids' sweeps
+    four-sweep marches with 4 rows per wave and up to 22 or 74 planes per
+    block (the chunk that fills the device) or 4; one point per thread with 64x16 threads and small grids' sweeps
     all in one workgroup's LDS) and 5 host-CPU cache-block shapes."""
     out = [Variant(AO_TARGET_GPU, f, bx, by, bz, fl) for f, bx, by, bz, fl in JACOBI_SWEEP_GPU]
     out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]

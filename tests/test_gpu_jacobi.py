@@ -371,3 +371,55 @@ def test_direct_family_small_grids_in_lds(env, orc, shape, S):
             torch.cuda.synchronize()
             _check((out if resident else oh).cpu().numpy(), want)
     ao.region_destroy(h)
+
+
+# (family, rows per wave, planes bound, flags: 1 streaming stores, 2 early
+# next-plane loads, 8 staged level 0)
+FILL = [("ZREG", 4, 32, 0), ("ZREG", 1, 9, 1), ("T2", 4, 32, 0), ("T2", 2, 17, 2),
+        ("T3", 4, 22, 8), ("T3", 1, 8, 0), ("T4", 4, 74, 9), ("T4", 2, 16, 2), ("T4", 5, 40, 8)]
+
+
+@pytest.mark.parametrize("shape,S", [((200, 300, 100), 10), ((130, 37, 41), 7), ((64, 64, 64), 5),
+                                     ((257, 65, 33), 9), ((62, 6, 1), 3), ((3, 2, 130), 4)])
+def test_fill_z_every_family(env, orc, shape, S):
+    # AO_VF_FILL_Z: each launch cuts z into the chunks that fill the device
+    # (at most bz planes each); the result stays bit-identical to the oracle
+    # for every register z-march family, with the S mod T remaining sweeps
+    # first (their launch fills the device the same way)
+    ao, torch, dev, st = env
+    fams = {"ZREG": ao.FAM_JACOBI_ZREG, "T2": ao.FAM_JACOBI_ZREG_T2,
+            "T3": ao.FAM_JACOBI_ZREG_T3, "T4": ao.FAM_JACOBI_ZREG_T4}
+    nx, ny, nz = shape
+    u0_h = synth.grid_u01(nx, ny, nz, seed=91 + nx + S)
+    want = orc.jacobi7(u0_h, nx, ny, nz, S)
+    u0 = torch.from_numpy(u0_h).to(dev)
+    out = torch.empty_like(u0)
+    vs = [ao.Variant(ao.AO_TARGET_GPU, fams[f], 64, r, bz, fl | ao.AO_VF_FILL_Z)
+          for f, r, bz, fl in FILL]
+    h = ao.region_declare_variants(f"gpu_fill_{nx}_{ny}_{nz}_{S}", ao.AO_JACOBI7_F64, vs,
+                                   model_type="roundrobin")
+    a = ao.jacobi_args(u0, out, nx, ny, nz, S)
+    for v, var in enumerate(vs):
+        planes = ao.ao_jacobi_planes(var, nx, ny, nz)
+        assert 1 <= planes <= min(var.bz, nz)
+        out.fill_(-1.0)
+        ao.region_run(h, a, stream=st, variant=v)
+        torch.cuda.synchronize()
+        _check(out.cpu().numpy(), want)
+    ao.region_destroy(h)
+
+
+def test_fill_z_device_picks(env):
+    # the device's own residency: two four-sweep workgroups (239 VGPRs, 56
+    # KB of LDS) per CU on 256 CUs keep 512^3 at 74 planes per block and cut
+    # 256^3 into 6 chunks of 43 (480 blocks, one round)
+    ao, torch, dev, st = env
+    v3 = ao.jacobi_variants_sweep()[3]
+    assert v3.flags & ao.AO_VF_FILL_Z
+    cus = ao.ao_device_cus()
+    got = {n: ao.ao_jacobi_planes(v3, n, n, n) for n in (64, 128, 256, 512)}
+    print("CUs", cus, "planes of the four-sweep variant", got, flush=True)
+    for n, p in got.items():
+        assert 1 <= p <= min(74, n)
+    if cus == 256:
+        assert got[512] == 74 and got[256] == 43

@@ -138,6 +138,9 @@ def staged_waves_grid(T, R, nx, ny, nz, bz, waves=4):
     (3, 1, (70, 5, 9), 1),
     (3, 6, (96, 50, 30), 16),
     (4, 5, (150, 48, 30), 74),    # more rows than the boundary waves stage: inner waves only
+    (4, 4, (130, 40, 9), 1),      # one-plane chunks (the device-filling chunk of small grids)
+    (4, 4, (130, 40, 9), 2),      # and two-plane chunks with a ragged last one
+    (3, 4, (130, 40, 7), 3),
 ])
 def test_per_grid_staged_addressing(T, R, shape, bz):
     nx, ny, nz = shape
