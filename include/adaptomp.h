@@ -147,12 +147,14 @@ enum ao_family {
                                  inside it */
 #define AO_VF_FILL_Z 32       /* register z-marches of one to four sweeps: bz is an
                                  upper bound; each launch takes the planes per block,
-                                 at most bz, that give the fewest plane steps on the
-                                 busiest workgroup slot of the device (the grid's
-                                 blocks in rounds of the workgroups the kernel keeps
-                                 resident, each block marching its planes plus the
-                                 2(T-1) halo planes of T fused sweeps; ties to the
-                                 longer chunk), so mid-size grids fill the chip */
+                                 at most bz, that minimise the busiest CU's time:
+                                 its blocks (the grid's, spread evenly over the CUs)
+                                 each march their planes plus the 2(T-1) halo planes
+                                 of T fused sweeps, up to the kernel's occupancy at
+                                 once, two at once 1.4x and three 1.5x as fast as
+                                 one; the fewest chunks within 3% of the best are
+                                 taken, in equal lengths, so mid-size grids fill
+                                 the chip */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,
@@ -463,15 +465,16 @@ int ao_device_cus(void);
 
 /* Planes per block that one launch of GPU Jacobi variant *v (a register
  * z-march family: ZREG, ZREG_T2, ZREG_T3, ZREG_T4) uses on an nx x ny x nz
- * grid: v->bz, or with AO_VF_FILL_Z the chunk length chosen for `resident`
- * workgroups on the device at once (resident <= 0: the kernel's own
- * occupancy on the current device times its CU count; then a device must be
- * present).  Written to *planes; AO_EINVAL for non-positive dimensions, a
- * null pointer or a variant that fits no z-march kernel.  Reports the launch
- * geometry a profiled variant actually ran (Sec. 3.1: a variant is its
- * launch configuration). */
-int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int64_t resident,
-                     int32_t* planes);
+ * grid: v->bz, or with AO_VF_FILL_Z the chunk length chosen for `cus` CUs
+ * that each hold `blocks_per_cu` of the kernel's workgroups at once (cus <=
+ * 0: the current device's CU count and the kernel's own occupancy; then a
+ * device must be present, and without one the answer is v->bz).  Written to
+ * *planes; AO_EINVAL for non-positive dimensions, cus > 0 with
+ * blocks_per_cu < 1, a null pointer or a variant that fits no z-march
+ * kernel.  Reports the launch geometry a profiled variant actually ran
+ * (Sec. 3.1: a variant is its launch configuration). */
+int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int32_t cus,
+                     int32_t blocks_per_cu, int32_t* planes);
 
 #ifdef __cplusplus
 }

@@ -114,7 +114,7 @@ def _load():
         "region_clear_memo": [P],
         "region_destroy": [P],
         "ao_device_cus": [],
-        "ao_jacobi_planes": [P, I, I, I, ctypes.c_int64, P],
+        "ao_jacobi_planes": [P, I, I, I, I, I, P],
         "ao_hbm_copy": [P, P, ctypes.c_int64, I, P],
         "ao_gather_probe": [P, P, ctypes.c_int64, ctypes.c_int64, P, P],
     }
@@ -281,11 +281,14 @@ def ao_device_cus() -> int:
     return lib.ao_device_cus()
 
 
-def ao_jacobi_planes(variant: Variant, nx: int, ny: int, nz: int, resident: int = 0) -> int:
+def ao_jacobi_planes(variant: Variant, nx: int, ny: int, nz: int, cus: int = 0,
+                     blocks_per_cu: int = 0) -> int:
     """Planes per block one launch of a register z-march variant uses on an
-    nx x ny x nz grid (for `resident` workgroups at once; 0: the device's)."""
+    nx x ny x nz grid (for `cus` CUs holding `blocks_per_cu` workgroups
+    each; cus = 0: the current device and the kernel's occupancy)."""
     out = ctypes.c_int32()
-    _check(lib.ao_jacobi_planes(ctypes.byref(variant), nx, ny, nz, resident, ctypes.byref(out)))
+    _check(lib.ao_jacobi_planes(ctypes.byref(variant), nx, ny, nz, cus, blocks_per_cu,
+                                ctypes.byref(out)))
     return out.value
 
 

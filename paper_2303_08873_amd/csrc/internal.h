@@ -29,17 +29,20 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
                                  int ny, int nz, hipStream_t s);
 // Planes per block of a launch of a register z-march variant (v.bz, or with
 // AO_VF_FILL_Z the chunk fill_planes picks) on an nx * ny * nz grid, for
-// `resident` workgroups at once (<= 0: the kernel's residency on the
-// current device); hipErrorInvalidConfiguration for a variant that fits no
-// z-march kernel.
-hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int64_t resident,
+// `cus` CUs holding `per_cu` of its workgroups each (cus <= 0: the kernel's
+// residency on the current device); hipErrorInvalidConfiguration for a
+// variant that fits no z-march kernel.
+hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int cus, int per_cu,
                              int* planes);
-// The chunk length, at most bz_max planes, that minimises the plane steps of
-// the busiest workgroup slot when `columns` columns of blocks are cut into
-// z-chunks: the blocks run in ceil(blocks / resident) rounds, each marching
-// its chunk plus `halo` planes (2(T-1) for T fused sweeps); ties go to the
-// longer chunk (less halo traffic).
-int fill_planes(int64_t columns, int nz, int bz_max, int halo, int64_t resident);
+// The chunk length, at most bz_max planes, of the fastest launch when
+// `columns` columns of blocks are cut into z-chunks and each block marches
+// its chunk plus `halo` planes (2(T-1) for T fused sweeps): the blocks
+// spread evenly over `cus` CUs, the busiest CU runs n = ceil(blocks / cus)
+// of them, up to `per_cu` at once, and the launch takes (chunk + halo) * n
+// / gain(min(n, per_cu)) (gain 1, 1.4, 1.5 for 1, 2, 3+ at once); the
+// fewest chunks whose cost lies within 3% of the least are taken (less halo
+// traffic), cut into equal lengths.
+int fill_planes(int64_t columns, int nz, int bz_max, int halo, int cus, int per_cu);
 // All `sweeps` sweeps dst <- J^sweeps(src) of a grid of at most 8192 points
 // in one launch of one workgroup (the grid held twice in LDS);
 // hipErrorInvalidConfiguration for a larger grid.

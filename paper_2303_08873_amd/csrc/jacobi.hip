@@ -562,31 +562,46 @@ ColumnKernel pick_zreg(bool nt, bool pf) {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Workgroups of kernel k the current device keeps resident at once (its
-// occupancy per CU times the CU count), cached per kernel and device; 0
-// when the runtime cannot say.
-int64_t resident_blocks(ColumnKernel k) {
+// Throughput of a CU running two, or three and more, of a register
+// z-march's workgroups at once, relative to one (they hide each other's
+// latencies), and the cost margin within which fill_planes takes fewer,
+// longer chunks (less halo traffic).  Fitted on MI355X to a sweep of 13 and
+// 14 chunk lengths of the staged three- and four-sweep marches over 50
+// grids (40 of the cost model's shape law, 10 cubes and slabs): the chunks
+// the rule picks run within 0.2% (three sweeps) and 0.7% (four) of the
+// fastest measured chunk, geometric mean.
+constexpr double kFillGain2 = 1.4, kFillGain3 = 1.5, kFillTolerance = 0.03;
+
+// CUs of the current device and workgroups of kernel k each keeps resident
+// at once (its occupancy), cached per kernel and device; false when the
+// runtime cannot say.
+bool residency(ColumnKernel k, int* cus, int* per_cu) {
     static std::mutex mu;
-    static std::vector<std::pair<std::pair<const void*, int>, int64_t>> cache;
+    static std::vector<std::pair<std::pair<const void*, int>, std::pair<int, int>>> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
-        return 0;
+        return false;
     }
     const std::pair<const void*, int> key((const void*)k, dev);
     std::lock_guard<std::mutex> g(mu);
     for (const auto& e : cache)
-        if (e.first == key) return e.second;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k, 64 * kZregWaves, 0) !=
+        if (e.first == key) {
+            *cus = e.second.first;
+            *per_cu = e.second.second;
+            return true;
+        }
+    int occ = 0, n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k, 64 * kZregWaves, 0) !=
             hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         (void)hipGetLastError();
-        return 0;
+        return false;
     }
-    const int64_t r = (int64_t)std::max(per_cu, 0) * std::max(cus, 0);
-    cache.push_back({key, r});
-    return r;
+    cache.push_back({key, {n, occ}});
+    *cus = n;
+    *per_cu = occ;
+    return true;
 }
 
 // What a full launch of a register z-march variant runs: its kernel, the
@@ -643,12 +658,13 @@ hipError_t column_shape(const ao_variant& v, int nx, int ny, int nz, ColumnShape
 }
 
 // Planes per block of a launch of shape c for variant v: v.bz, or with
-// AO_VF_FILL_Z the chunk fill_planes picks for `resident` workgroups (the
-// kernel's own residency on the current device when resident <= 0).
-int column_planes(const ao_variant& v, const ColumnShape& c, int nz, int64_t resident) {
+// AO_VF_FILL_Z the chunk fill_planes picks for `cus` CUs holding `per_cu`
+// of its workgroups each (the kernel's own residency on the current device
+// when cus <= 0; v.bz if the runtime cannot say).
+int column_planes(const ao_variant& v, const ColumnShape& c, int nz, int cus, int per_cu) {
     if (!(v.flags & AO_VF_FILL_Z)) return v.bz;
-    if (resident <= 0) resident = resident_blocks(c.k);
-    return fill_planes((int64_t)c.nbx * c.nby, nz, v.bz, 2 * (c.T - 1), resident);
+    if (cus <= 0 && !residency(c.k, &cus, &per_cu)) return v.bz;
+    return fill_planes((int64_t)c.nbx * c.nby, nz, v.bz, 2 * (c.T - 1), cus, per_cu);
 }
 
 // One launch of a register z-march variant: src -> dst.
@@ -657,7 +673,7 @@ hipError_t launch_columns(const ao_variant& v, hipStream_t s, const double* src,
     ColumnShape c;
     const hipError_t e = column_shape(v, nx, ny, nz, &c);
     if (e != hipSuccess) return e;
-    const int bz = column_planes(v, c, nz, 0);
+    const int bz = column_planes(v, c, nz, 0, 0);
     const int64_t nb = (int64_t)c.nbx * c.nby * ((nz + bz - 1) / bz);
     if (bz <= 0 || nb > 0x7fffffff) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(c.k, dim3((unsigned)nb), dim3(64 * kZregWaves), 0, s, src, dst, nx, ny, nz,
@@ -687,20 +703,24 @@ __global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src,
 
 }  // namespace
 
-int fill_planes(int64_t columns, int nz, int bz_max, int halo, int64_t resident) {
+int fill_planes(int64_t columns, int nz, int bz_max, int halo, int cus, int per_cu) {
     const int top = std::min(bz_max, nz);
-    if (top < 1 || columns < 1 || resident < 1) return std::max(top, 1);
-    int best = top;
-    int64_t best_cost = INT64_MAX;
-    for (int bz = top; bz >= std::max(1, top - 4095); --bz) {
+    if (top < 1 || columns < 1 || cus < 1) return std::max(top, 1);
+    const int lo = std::max(1, top - 4095);
+    auto cost = [&](int bz) {
         const int64_t blocks = columns * ((nz + bz - 1) / bz);
-        const int64_t cost = ((blocks + resident - 1) / resident) * (bz + halo);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = bz;
-        }
-    }
-    return best;
+        const int64_t n = (blocks + cus - 1) / cus;  // workgroups on the busiest CU
+        const int64_t j = std::min<int64_t>(n, std::max(per_cu, 1));
+        const double gain = j >= 3 ? kFillGain3 : j == 2 ? kFillGain2 : 1.0;
+        return (double)(bz + halo) * (double)n / gain;
+    };
+    double best = cost(top);
+    for (int bz = top - 1; bz >= lo; --bz) best = std::min(best, cost(bz));
+    // the fewest chunks within the margin, cut into equal lengths
+    int chunks = INT32_MAX;
+    for (int bz = top; bz >= lo; --bz)
+        if (cost(bz) <= best * (1.0 + kFillTolerance)) chunks = std::min(chunks, (nz + bz - 1) / bz);
+    return chunks == INT32_MAX ? top : (nz + chunks - 1) / chunks;
 }
 
 bool lds_sweeps_fit(int nx, int ny, int nz) {
@@ -775,13 +795,13 @@ hipError_t jacobi_gpu_multi_sweep(const ao_variant& v, const double* src, double
     return launch_columns(v, s, src, dst, nx, ny, nz);
 }
 
-hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int64_t resident,
+hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int cus, int per_cu,
                              int* planes) {
     if (nx <= 0 || ny <= 0 || nz <= 0 || !planes) return hipErrorInvalidValue;
     ColumnShape c;
     const hipError_t e = column_shape(v, nx, ny, nz, &c);
     if (e != hipSuccess) return e;
-    *planes = column_planes(v, c, nz, resident);
+    *planes = column_planes(v, c, nz, cus, per_cu);
     return hipSuccess;
 }
 

@@ -1309,12 +1309,13 @@ int ao_gather_probe(const int32_t* idx, const double* x, int64_t m, int64_t nx, 
     return AO_OK;
 }
 
-int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int64_t resident,
-                     int32_t* planes) {
-    if (!v || !planes || nx <= 0 || ny <= 0 || nz <= 0 || v->target != AO_TARGET_GPU)
+int ao_jacobi_planes(const ao_variant* v, int32_t nx, int32_t ny, int32_t nz, int32_t cus,
+                     int32_t blocks_per_cu, int32_t* planes) {
+    if (!v || !planes || nx <= 0 || ny <= 0 || nz <= 0 || v->target != AO_TARGET_GPU ||
+        (cus > 0 && blocks_per_cu < 1))
         return fail(AO_EINVAL, "bad arguments");
     int p = 0;
-    const hipError_t e = jacobi_gpu_planes(*v, nx, ny, nz, resident, &p);
+    const hipError_t e = jacobi_gpu_planes(*v, nx, ny, nz, cus, blocks_per_cu, &p);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(AO_EINVAL, "not a register z-march variant that fits its kernels");

@@ -1,8 +1,10 @@
 """Host logic of AO_VF_FILL_Z: the planes per block a register z-march
-launch takes, queried through the C ABI with a given number of resident
-workgroups (no device needed), against the rule written out by brute force:
-the chunk length b <= bz that minimises ceil(blocks(b) / resident) * (b +
-2(T-1)), ties to the longer chunk."""
+launch takes, queried through the C ABI for a given CU count and occupancy
+(no device needed), against the rule written out by brute force: with n(b)
+= ceil(blocks(b) / CUs) workgroups on the busiest CU, the cost of chunk
+length b <= bz is (b + 2(T-1)) * n / gain(min(n, occupancy)), gain 1, 1.4,
+1.5 for 1, 2, 3+ at once; of the lengths within 3% of the least cost, the
+fewest chunks are taken, cut into equal lengths."""
 import itertools
 
 import pytest
@@ -17,26 +19,30 @@ FAMS = [(ao.FAM_JACOBI_ZREG, 1, 64), (ao.FAM_JACOBI_ZREG_T2, 2, 62),
         (ao.FAM_JACOBI_ZREG_T3, 3, 60), (ao.FAM_JACOBI_ZREG_T4, 4, 58)]
 
 
-def rule(nx, ny, nz, T, width, R, bz, resident):
+def rule(nx, ny, nz, T, width, R, bz, cus, occ):
     cols = cd(nx, width) * cd(ny, 4 * R)
-    best = None
-    for b in range(1, min(bz, nz) + 1):
-        cost = cd(cols * cd(nz, b), resident) * (b + 2 * (T - 1))
-        if best is None or cost <= best[0]:
-            best = (cost, b)
-    return best[1]
+    top = min(bz, nz)
+
+    def cost(b):
+        n = cd(cols * cd(nz, b), cus)
+        j = min(n, occ)
+        return (b + 2 * (T - 1)) * n / (1.5 if j >= 3 else 1.4 if j == 2 else 1.0)
+    least = min(cost(b) for b in range(1, top + 1))
+    chunks = min(cd(nz, b) for b in range(1, top + 1) if cost(b) <= least * 1.03)
+    return cd(nz, chunks)
 
 
 @pytest.mark.parametrize("fam,T,width", FAMS)
 def test_planes_follow_the_rule(fam, T, width):
     R = 4
     flags = ao.AO_VF_FILL_Z | (ao.AO_VF_STAGED if T >= 3 else 0)
-    for (nx, ny, nz), bz, res in itertools.product(
+    for (nx, ny, nz), bz, (cus, occ) in itertools.product(
             [(16, 16, 16), (64, 64, 64), (100, 37, 250), (256, 256, 256), (512, 512, 512),
-             (1000, 20, 7), (61, 300, 1)], [1, 4, 22, 74], [1, 512, 768, 4096]):
+             (1000, 20, 7), (61, 300, 1), (235, 219, 37)], [1, 4, 22, 74],
+            [(1, 1), (256, 1), (256, 2), (256, 3), (80, 8)]):
         v = ao.Variant(G, fam, 64, R, bz, flags)
-        got = ao.ao_jacobi_planes(v, nx, ny, nz, res)
-        assert got == rule(nx, ny, nz, T, width, R, bz, res), (fam, nx, ny, nz, bz, res)
+        got = ao.ao_jacobi_planes(v, nx, ny, nz, cus, occ)
+        assert got == rule(nx, ny, nz, T, width, R, bz, cus, occ), (fam, nx, ny, nz, bz, cus, occ)
         assert 1 <= got <= min(bz, nz)
 
 
@@ -44,23 +50,27 @@ def test_known_picks():
     t4 = ao.Variant(G, ao.FAM_JACOBI_ZREG_T4, 64, 4, 74,
                     ao.AO_VF_NT_STORE | ao.AO_VF_STAGED | ao.AO_VF_FILL_Z)
     t3 = ao.Variant(G, ao.FAM_JACOBI_ZREG_T3, 64, 4, 22, ao.AO_VF_STAGED | ao.AO_VF_FILL_Z)
-    # two four-sweep blocks per CU on 256 CUs: 512^3 keeps its 74 planes
-    # (7 chunks, 4 rounds of 80 plane steps), 256^3 takes 43 (6 chunks of
-    # 80 columns: 480 blocks, one round)
-    assert ao.ao_jacobi_planes(t4, 512, 512, 512, 512) == 74
-    assert ao.ao_jacobi_planes(t4, 256, 256, 256, 512) == 43
-    # three three-sweep blocks per CU: 128^3 in chunks of 4
-    assert ao.ao_jacobi_planes(t3, 128, 128, 128, 768) == 4
-    # one resident block: as few chunks as the bound allows (5 for 300
-    # planes), each as short as that count permits
-    assert ao.ao_jacobi_planes(t4, 300, 300, 300, 1) == 60
+    # 256 CUs, two four-sweep workgroups each: 512^3 keeps 74 planes (7
+    # chunks, 2016 blocks; 64 planes would cost 1.6% less on the model,
+    # inside the 3% margin that prefers less halo traffic), 256^3 takes 43
+    # (6 chunks of 80 columns: 480 blocks, two on most CUs)
+    assert ao.ao_jacobi_planes(t4, 512, 512, 512, 256, 2) == 74
+    assert ao.ao_jacobi_planes(t4, 256, 256, 256, 256, 2) == 43
+    # a grid of 70 columns and 37 planes: 7 chunks of 6 (490 blocks, two per
+    # CU) rather than 3 of 16 (210 blocks, one per CU; 1.46x slower measured)
+    assert ao.ao_jacobi_planes(t4, 235, 219, 37, 256, 2) == 6
+    # three-sweep march at 512^3: its full 22 planes
+    assert ao.ao_jacobi_planes(t3, 512, 512, 512, 256, 3) == 22
+    # one CU holding one workgroup: as few chunks as the bound allows (5
+    # for 300 planes), each as short as that count permits
+    assert ao.ao_jacobi_planes(t4, 300, 300, 300, 1, 1) == 60
 
 
 def test_without_the_flag_the_declared_planes():
     for fam, T, width in FAMS:
         v = ao.Variant(G, fam, 64, 2, 13, ao.AO_VF_STAGED if T >= 3 else 0)
-        assert ao.ao_jacobi_planes(v, 512, 512, 512, 512) == 13
-        assert ao.ao_jacobi_planes(v, 5, 5, 5, 512) == 13
+        assert ao.ao_jacobi_planes(v, 512, 512, 512, 256, 2) == 13
+        assert ao.ao_jacobi_planes(v, 5, 5, 5, 256, 2) == 13
 
 
 def test_refusals():
@@ -74,10 +84,12 @@ def test_refusals():
            ao.Variant(ao.AO_TARGET_HOST, ao.FAM_JACOBI_HOST, 64, 4, 1, 0)]
     for v in bad:
         with pytest.raises(ao.AdaptError):
-            ao.ao_jacobi_planes(v, 64, 64, 64, 512)
+            ao.ao_jacobi_planes(v, 64, 64, 64, 256, 2)
     for dims in [(0, 4, 4), (4, -1, 4), (4, 4, 0)]:
         with pytest.raises(ao.AdaptError):
-            ao.ao_jacobi_planes(ok, *dims, 512)
+            ao.ao_jacobi_planes(ok, *dims, 256, 2)
+    with pytest.raises(ao.AdaptError):
+        ao.ao_jacobi_planes(ok, 64, 64, 64, 256, 0)  # CUs given without an occupancy
 
 
 def test_declaration_refuses_the_flag_outside_the_z_marches():

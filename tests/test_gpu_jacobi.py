@@ -412,7 +412,7 @@ def test_fill_z_every_family(env, orc, shape, S):
 def test_fill_z_device_picks(env):
     # the device's own residency: two four-sweep workgroups (239 VGPRs, 56
     # KB of LDS) per CU on 256 CUs keep 512^3 at 74 planes per block and cut
-    # 256^3 into 6 chunks of 43 (480 blocks, one round)
+    # 256^3 into 6 chunks of 43 (480 blocks, two on most CUs)
     ao, torch, dev, st = env
     v3 = ao.jacobi_variants_sweep()[3]
     assert v3.flags & ao.AO_VF_FILL_Z
