@@ -22,7 +22,7 @@ def jacobi_variants_blocks():
 JACOBI_SWEEP_GPU = [(FAM_JACOBI_ZREG_T3, 64, 1, 1, AO_VF_STAGED), (FAM_JACOBI_DIRECT, 64, 4, 1, 0),
                     (FAM_JACOBI_ZREG_T3, 64, 4, 22, AO_VF_STAGED | AO_VF_FILL_Z),
                     (FAM_JACOBI_ZREG_T4, 64, 4, 74, AO_VF_NT_STORE | AO_VF_STAGED | AO_VF_FILL_Z),
-                    (FAM_JACOBI_ZREG_T3, 64, 4, 4, AO_VF_STAGED),
+                    (FAM_JACOBI_ZREG_T3, 64, 2, 22, AO_VF_STAGED | AO_VF_FILL_Z),
                     (FAM_JACOBI_DIRECT, 64, 16, 1, AO_VF_LDS_SWEEPS)]
 JACOBI_SWEEP_HOST = [(0, 1), (256, 4), (64, 16), (0, 8), (128, 32)]
 STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
@@ -31,10 +31,13 @@ STATIC_DEFAULT = 1  # 64x4 = 256 threads, the OpenMP offload default team size
 def jacobi_variants_sweep():
     """11 variants: 6 GPU kernels (the three-sweep register z-march with
     level 0 staged, 1 row per wave and 1 plane per block for small grids;
-    one point per thread with 64x4 threads, the static default; three- and
-    four-sweep marches with 4 rows per wave and up to 22 or 74 planes per
-    block (the chunk that fills the device) or 4; one point per thread with 64x16 threads and small grids' sweeps
-    all in one workgroup's LDS) and 5 host-CPU cache-block shapes."""
+    one point per thread with 64x4 threads, the static default; the staged
+    three-sweep march with 4 rows per wave and up to 22 planes per block,
+    the staged four-sweep march with 4 rows and up to 74 planes, and the
+    staged three-sweep march with 2 rows and up to 22 planes, each launch
+    taking the chunk that fills the device; one point per thread with 64x16
+    threads and small grids' sweeps all in one workgroup's LDS) and 5
+    host-CPU cache-block shapes."""
     out = [Variant(AO_TARGET_GPU, f, bx, by, bz, fl) for f, bx, by, bz, fl in JACOBI_SWEEP_GPU]
     out += [Variant(AO_TARGET_HOST, FAM_JACOBI_HOST, bx, by, 1, 0) for bx, by in JACOBI_SWEEP_HOST]
     return out

@@ -141,6 +141,7 @@ def staged_waves_grid(T, R, nx, ny, nz, bz, waves=4):
     (4, 4, (130, 40, 9), 1),      # one-plane chunks (the device-filling chunk of small grids)
     (4, 4, (130, 40, 9), 2),      # and two-plane chunks with a ragged last one
     (3, 4, (130, 40, 7), 3),
+    (3, 2, (130, 21, 11), 2),     # two rows per wave, filled chunks
 ])
 def test_per_grid_staged_addressing(T, R, shape, bz):
     nx, ny, nz = shape
