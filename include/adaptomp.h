@@ -150,11 +150,11 @@ enum ao_family {
                                  at most bz, that minimise the busiest CU's time:
                                  its blocks (the grid's, spread evenly over the CUs)
                                  each march their planes plus the 2(T-1) halo planes
-                                 of T fused sweeps, up to the kernel's occupancy at
-                                 once, two at once 1.4x and three 1.5x as fast as
-                                 one; the fewest chunks within 3% of the best are
-                                 taken, in equal lengths, so mid-size grids fill
-                                 the chip */
+                                 of T fused sweeps, in rounds of the kernel's
+                                 occupancy and a last partial round, two at once
+                                 1.4x and three 1.5x as fast as one; the fewest
+                                 chunks within 3% of the best are taken, in equal
+                                 lengths, so mid-size grids fill the chip */
 
 /* One variant.  Ids are positions in the declaration array (0-based), as
  * categorical variants are numbered in declaration order (Sec. 3.1,

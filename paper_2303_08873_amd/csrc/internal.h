@@ -38,10 +38,10 @@ hipError_t jacobi_gpu_planes(const ao_variant& v, int nx, int ny, int nz, int cu
 // `columns` columns of blocks are cut into z-chunks and each block marches
 // its chunk plus `halo` planes (2(T-1) for T fused sweeps): the blocks
 // spread evenly over `cus` CUs, the busiest CU runs n = ceil(blocks / cus)
-// of them, up to `per_cu` at once, and the launch takes (chunk + halo) * n
-// / gain(min(n, per_cu)) (gain 1, 1.4, 1.5 for 1, 2, 3+ at once); the
-// fewest chunks whose cost lies within 3% of the least are taken (less halo
-// traffic), cut into equal lengths.
+// of them in rounds of k = per_cu at once and a last round of n mod k, a
+// round of j taking (chunk + halo) * j / gain(j) (gain 1, 1.4, 1.5 for 1,
+// 2, 3+ at once); the fewest chunks whose cost lies within 3% of the least
+// are taken (less halo traffic), cut into equal lengths.
 int fill_planes(int64_t columns, int nz, int bz_max, int halo, int cus, int per_cu);
 // All `sweeps` sweeps dst <- J^sweeps(src) of a grid of at most 8192 points
 // in one launch of one workgroup (the grid held twice in LDS);

@@ -567,9 +567,9 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // latencies), and the cost margin within which fill_planes takes fewer,
 // longer chunks (less halo traffic).  Fitted on MI355X to a sweep of 13 and
 // 14 chunk lengths of the staged three- and four-sweep marches over 50
-// grids (40 of the cost model's shape law, 10 cubes and slabs): the chunks
-// the rule picks run within 0.2% (three sweeps) and 0.7% (four) of the
-// fastest measured chunk, geometric mean.
+// grids (40 of the cost model's shape law, 10 cubes and slabs): among the
+// measured lengths the rule's picks run within 0.3% (three sweeps) and
+// 0.4% (four) of the fastest, geometric mean.
 constexpr double kFillGain2 = 1.4, kFillGain3 = 1.5, kFillTolerance = 0.03;
 
 // CUs of the current device and workgroups of kernel k each keeps resident
@@ -707,12 +707,15 @@ int fill_planes(int64_t columns, int nz, int bz_max, int halo, int cus, int per_
     const int top = std::min(bz_max, nz);
     if (top < 1 || columns < 1 || cus < 1) return std::max(top, 1);
     const int lo = std::max(1, top - 4095);
+    const int64_t k = std::max(per_cu, 1);
+    auto gain = [](int64_t j) { return j >= 3 ? kFillGain3 : j == 2 ? kFillGain2 : 1.0; };
     auto cost = [&](int bz) {
         const int64_t blocks = columns * ((nz + bz - 1) / bz);
         const int64_t n = (blocks + cus - 1) / cus;  // workgroups on the busiest CU
-        const int64_t j = std::min<int64_t>(n, std::max(per_cu, 1));
-        const double gain = j >= 3 ? kFillGain3 : j == 2 ? kFillGain2 : 1.0;
-        return (double)(bz + halo) * (double)n / gain;
+        // rounds of k at once, then the n mod k left over
+        const int64_t full = n / k, r = n % k;
+        return (double)(bz + halo) *
+               ((double)(full * k) / gain(k) + (r ? (double)r / gain(r) : 0.0));
     };
     double best = cost(top);
     for (int bz = top - 1; bz >= lo; --bz) best = std::min(best, cost(bz));

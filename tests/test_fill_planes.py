@@ -1,10 +1,11 @@
 """Host logic of AO_VF_FILL_Z: the planes per block a register z-march
 launch takes, queried through the C ABI for a given CU count and occupancy
 (no device needed), against the rule written out by brute force: with n(b)
-= ceil(blocks(b) / CUs) workgroups on the busiest CU, the cost of chunk
-length b <= bz is (b + 2(T-1)) * n / gain(min(n, occupancy)), gain 1, 1.4,
-1.5 for 1, 2, 3+ at once; of the lengths within 3% of the least cost, the
-fewest chunks are taken, cut into equal lengths."""
+= ceil(blocks(b) / CUs) workgroups on the busiest CU, run in rounds of k =
+occupancy and a last round of n mod k, a round of j costing (b + 2(T-1)) *
+j / gain(j) with gain 1, 1.4, 1.5 for 1, 2, 3+ at once; of the chunk
+lengths b <= bz within 3% of the least cost, the fewest chunks are taken,
+cut into equal lengths."""
 import itertools
 
 import pytest
@@ -23,10 +24,13 @@ def rule(nx, ny, nz, T, width, R, bz, cus, occ):
     cols = cd(nx, width) * cd(ny, 4 * R)
     top = min(bz, nz)
 
+    def gain(j):
+        return 1.5 if j >= 3 else 1.4 if j == 2 else 1.0
+
     def cost(b):
         n = cd(cols * cd(nz, b), cus)
-        j = min(n, occ)
-        return (b + 2 * (T - 1)) * n / (1.5 if j >= 3 else 1.4 if j == 2 else 1.0)
+        full, r = divmod(n, occ)
+        return (b + 2 * (T - 1)) * (full * occ / gain(occ) + (r / gain(r) if r else 0.0))
     least = min(cost(b) for b in range(1, top + 1))
     chunks = min(cd(nz, b) for b in range(1, top + 1) if cost(b) <= least * 1.03)
     return cd(nz, chunks)
@@ -59,6 +63,9 @@ def test_known_picks():
     # a grid of 70 columns and 37 planes: 7 chunks of 6 (490 blocks, two per
     # CU) rather than 3 of 16 (210 blocks, one per CU; 1.46x slower measured)
     assert ao.ao_jacobi_planes(t4, 235, 219, 37, 256, 2) == 6
+    # 320^3 (120 columns): 8 chunks of 40 (960 blocks: two rounds of two
+    # per CU), not 6 of 54 (720: a round of two, then one alone)
+    assert ao.ao_jacobi_planes(t4, 320, 320, 320, 256, 2) == 40
     # three-sweep march at 512^3: its full 22 planes
     assert ao.ao_jacobi_planes(t3, 512, 512, 512, 256, 3) == 22
     # one CU holding one workgroup: as few chunks as the bound allows (5
