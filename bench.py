@@ -302,9 +302,8 @@ def batch_pmc_traffic(chosen):
     """HBM bytes per graph replay of the batched launch from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE over the graph's passes,
     scaled by the copy-probe calibration), when it was taken with these
-    kernel sources and the same tiles on the three largest size buckets
-    (maximum dimension above 32: all but a fraction of a percent of the
-    points)."""
+    kernel sources and the same tiles on the two largest size buckets
+    (maximum dimension above 64: 99% of the points)."""
     path = os.path.join(ROOT, "profiles", "batch_graph_pmc.json")
     try:
         with open(path) as fh:
@@ -313,7 +312,7 @@ def batch_pmc_traffic(chosen):
         return None
     if d.get("source_sha256") != source_digest(BATCH_SOURCES):
         return None
-    if list(d.get("autotuned_candidates", []))[2:] != list(chosen)[2:]:
+    if list(d.get("autotuned_candidates", []))[3:] != list(chosen)[3:]:
         return None
     return d.get("traffic_bytes_per_replay")
 

@@ -337,9 +337,13 @@ typedef struct ao_batch ao_batch; /* opaque, library-owned plan */
 int batch_create(const ao_args* inst, int count, ao_batch** out);
 
 /* Autotune: for each bucket time each candidate tile shape over the
- * bucket's instances (warmup + reps, median) and keep the fastest.  Writes
- * the chosen candidate index per bucket to chosen[5] (may be NULL; -1 =
- * empty bucket).  Synchronises; overwrites the instances' outputs. */
+ * bucket's instances (warmup + reps, median) and keep the fastest; then,
+ * largest bucket first, time each candidate again over the whole batch with
+ * every other bucket on its current tile and keep the fastest (the buckets
+ * share the persistent kernels, so the best tile alone can balance worse
+ * beside the others).  Writes the chosen candidate index per bucket to
+ * chosen[5] (may be NULL; -1 = empty bucket).  Synchronises; overwrites the
+ * instances' outputs. */
 int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen);
 
 /* Run every instance once: one persistent kernel per pass over the work

@@ -392,7 +392,7 @@ struct ao_batch {
     int launches_3 = 0;
     int items_per_bucket[kBuckets] = {0};
     double* scratch = nullptr;
-    int grid = 0;
+    int grid = 0, grid_f = 0, grid_3 = 0;  // workgroups of each persistent kernel
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -478,8 +478,8 @@ hipError_t launch_sweeps(ao_batch* b, hipStream_t s) {
             if (e != hipSuccess) return e;
         }
     }
-    const int grid = std::min(b->nitems, b->grid), grid_f = std::min(b->nitems_f, b->grid);
-    const int grid_3 = std::min(b->nitems_3, b->grid);
+    const int grid = std::min(b->nitems, b->grid), grid_f = std::min(b->nitems_f, b->grid_f);
+    const int grid_3 = std::min(b->nitems_3, b->grid_3);
     const int L = std::max(b->launches, std::max(b->launches_f, b->launches_3));
     for (int l = 0; l < L; ++l) {
         if (l < b->launches && b->nitems > 0)
@@ -559,7 +559,21 @@ int batch_create(const ao_args* inst, int count, ao_batch** out) {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    b->grid = std::max(1, cus) * 8;
+    // each persistent kernel runs as many workgroups as the device keeps
+    // resident at once, so no workgroup waits for another to finish before
+    // it starts striding over the items (8 per CU when the runtime cannot say)
+    auto resident = [&](const void* k) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) != hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 8;
+        }
+        return std::max(1, cus) * per_cu;
+    };
+    b->grid = resident((const void*)k_batch_sweep);
+    b->grid_f = resident((const void*)k_batch_fused);
+    b->grid_3 = resident((const void*)k_batch_fused3);
     int rc = rebuild(b.get());
     if (rc) return rc;
     *out = b.release();
@@ -573,36 +587,62 @@ int batch_autotune(ao_batch* b, void* stream, int warmup, int reps, int* chosen)
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return fail(AO_EHIP, "event creation");
+    // median time of one execution of the items currently uploaded
+    auto median_ms = [&](double* med) {
+        std::vector<double> ts;
+        for (int r = 0; r < warmup + reps && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_sweeps(b, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r >= warmup) ts.push_back(ms);
+        }
+        if (e != hipSuccess) return;
+        std::sort(ts.begin(), ts.end());
+        *med = ts.size() % 2 ? ts[ts.size() / 2]
+                             : 0.5 * (ts[ts.size() / 2 - 1] + ts[ts.size() / 2]);
+    };
     int result[kBuckets];
-    for (int k = 0; k < kBuckets; ++k) {
+    // first each bucket alone, every candidate tile
+    for (int k = 0; k < kBuckets && e == hipSuccess; ++k) {
         result[k] = -1;
         bool any = false;
         for (int bk : b->bucket) any = any || bk == k;
         if (!any) continue;
         double best = INFINITY;
-        for (int c = 0; c < kNumCands; ++c) {
+        for (int c = 0; c < kNumCands && e == hipSuccess; ++c) {
             e = upload_items(b, make_items(b, k, c));
-            std::vector<double> ts;
-            for (int r = 0; r < warmup + reps && e == hipSuccess; ++r) {
-                e = hipEventRecord(e0, s);
-                if (e == hipSuccess) e = launch_sweeps(b, s);
-                if (e == hipSuccess) e = hipEventRecord(e1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (r >= warmup) ts.push_back(ms);
-            }
-            if (e != hipSuccess) break;
-            std::sort(ts.begin(), ts.end());
-            const double med = ts.size() % 2 ? ts[ts.size() / 2]
-                                             : 0.5 * (ts[ts.size() / 2 - 1] + ts[ts.size() / 2]);
-            if (med < best) {
+            double med = INFINITY;
+            if (e == hipSuccess) median_ms(&med);
+            if (e == hipSuccess && med < best) {
                 best = med;
                 result[k] = c;
             }
         }
-        if (e != hipSuccess) break;
-        b->cand[k] = result[k];
+        if (e == hipSuccess) b->cand[k] = result[k];
+    }
+    // then each bucket again, largest first, timing the whole batch with
+    // every other bucket on its current tile: the buckets share the
+    // persistent kernels, so the tile a bucket runs best alone on (fewer,
+    // larger tiles) can balance worse beside the others
+    for (int k = kBuckets - 1; k >= 0 && e == hipSuccess; --k) {
+        if (result[k] < 0) continue;
+        double best = INFINITY;
+        int pick = result[k];
+        for (int c = 0; c < kNumCands && e == hipSuccess; ++c) {
+            b->cand[k] = c;
+            e = upload_items(b, make_items(b, -1, -1));
+            double med = INFINITY;
+            if (e == hipSuccess) median_ms(&med);
+            if (e == hipSuccess && med < best) {
+                best = med;
+                pick = c;
+            }
+        }
+        b->cand[k] = pick;
+        result[k] = pick;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
