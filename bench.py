@@ -541,10 +541,14 @@ def spmv_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
            "held_out_geomean_regret_pct": round(100 * (float(np.exp(np.mean(np.log(r)))) - 1), 3),
            "held_out": rows}
     v = ao.spmv_variants(xslice=(13, 14))[chosen]
+    vkey = f"family={v.family} bx={v.bx} by={v.by}"
+    traffic = spmv_pmc_traffic(vkey)
     res["roofline"] = {"bound": "hbm", "achieved": res["value"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(res["value"] / HBM_PEAK_GBS, 4),
-                       "traffic": None,
-                       "kernel": f"variant {chosen} (family={v.family} bx={v.bx} by={v.by}) at n=2^22"}
+                       "traffic": traffic,
+                       "traffic_frac": (round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+                                        if traffic else None),
+                       "kernel": f"variant {chosen} ({vkey}) at n=2^22"}
     if not no_cpu_baseline:
         import oracle
         h = {k: t[k].cpu().numpy() for k in ("row_ptr", "col", "val", "x")}
