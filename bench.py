@@ -300,10 +300,10 @@ def batch_workload(steps: int, warmup: int, no_cpu_baseline: bool = False):
 
 def batch_pmc_traffic(chosen):
     """HBM bytes per graph replay of the batched launch from the committed
-    counter summary (FETCH_SIZE + WRITE_SIZE over the graph's passes,
-    scaled by the copy-probe calibration), when it was taken with these
-    kernel sources and the same tiles on the two largest size buckets
-    (maximum dimension above 64: 99% of the points)."""
+    counter summaries (FETCH_SIZE + WRITE_SIZE over the graph's passes,
+    scaled by the copy-probe calibration): the one taken with these kernel
+    sources and the same tiles on the two largest size buckets (maximum
+    dimension above 64: 99% of the points), if any."""
     path = os.path.join(ROOT, "profiles", "batch_graph_pmc.json")
     try:
         with open(path) as fh:
@@ -312,9 +312,10 @@ def batch_pmc_traffic(chosen):
         return None
     if d.get("source_sha256") != source_digest(BATCH_SOURCES):
         return None
-    if list(d.get("autotuned_candidates", []))[3:] != list(chosen)[3:]:
-        return None
-    return d.get("traffic_bytes_per_replay")
+    for prof in d.get("profiles", []):
+        if list(prof.get("autotuned_candidates", []))[3:] == list(chosen)[3:]:
+            return prof.get("traffic_bytes_per_replay")
+    return None
 
 
 def batch_kernel_only(replays: int = 5, tiles=None):

@@ -57,4 +57,21 @@ def test_gates_refuse_other_variants_and_sources(monkeypatch):
     monkeypatch.setattr(bench, "source_digest", lambda names: "0" * 64)
     assert bench.spmv_pmc_traffic(key) is None
     assert bench.pmc_traffic(_load("jacobi_512_pmc.json")["variant"]) is None
-    assert bench.batch_pmc_traffic(_load("batch_graph_pmc.json")["autotuned_candidates"]) is None
+    for prof in _load("batch_graph_pmc.json")["profiles"]:
+        assert bench.batch_pmc_traffic(prof["autotuned_candidates"]) is None
+
+
+def test_batch_summaries_match_their_tiles():
+    d = _load("batch_graph_pmc.json")
+    current = bench.source_digest(bench.BATCH_SOURCES) == d["source_sha256"]
+    seen = set()
+    for prof in d["profiles"]:
+        key = tuple(prof["autotuned_candidates"][3:])
+        assert key not in seen  # one summary per tile pair of the large buckets
+        seen.add(key)
+        assert prof["traffic_bytes_per_replay"] == pytest.approx(
+            prof["fetch_bytes_per_replay"] + prof["write_bytes_per_replay"])
+        assert prof["traffic_bytes_per_replay"] >= prof["min_traffic_bytes_per_replay"]
+        got = bench.batch_pmc_traffic([0, 0, 0] + list(key))
+        assert got == (prof["traffic_bytes_per_replay"] if current else None)
+    assert bench.batch_pmc_traffic([0, 0, 0, -1, -1]) is None
