@@ -366,9 +366,17 @@ int bucket_of(int nx, int ny, int nz) {
     return 4;
 }
 
-int64_t item_cost(const Inst& in, const TileCfg& c) {
-    (void)in;
-    return (int64_t)c.tx * c.ty * c.tz;
+// Work of one item: the points of a one-point-per-thread tile inside the
+// grid; for the register marches, the waves that hold rows inside the grid
+// times the planes each marches (its chunk inside the grid plus the 2(T-1)
+// halo planes of T fused sweeps) -- a wave runs its whole 64-lane strip
+// whatever the columns inside the grid.
+int64_t item_cost(const Inst& in, const TileCfg& c, int x, int y, int z) {
+    const int64_t wx = std::min(c.tx, in.nx - x), wy = std::min(c.ty, in.ny - y),
+                  wz = std::min(c.tz, in.nz - z);
+    if (c.kind == kDirect) return wx * wy * wz;
+    const int R = c.kind % 10, T = is_tri(c.kind) ? 3 : is_fused(c.kind) ? 2 : 1;
+    return ((wy + R - 1) / R) * (wz + 2 * (T - 1));
 }
 
 }  // namespace
@@ -424,9 +432,10 @@ std::vector<Item> make_items(const ao_batch* b, int only_bucket, int cand_overri
         for (int z = 0; z < in.nz; z += c.tz)
             for (int y = 0; y < in.ny; y += c.ty)
                 for (int x = 0; x < in.nx; x += c.tx)
-                    v.push_back({item_cost(in, c), Item{(int32_t)q, x, y, z, cand}});
+                    v.push_back({item_cost(in, c, x, y, z), Item{(int32_t)q, x, y, z, cand}});
     }
-    // larger items first: the strided loop then ends with the small ones
+    // larger items first (the strided loop then ends with the small ones);
+    // upload_list deals them out in alternating directions
     std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
     std::vector<Item> out;
     out.reserve(v.size());
@@ -434,11 +443,18 @@ std::vector<Item> make_items(const ao_batch* b, int only_bucket, int cand_overri
     return out;
 }
 
-hipError_t upload_list(Item** d, int* count, const std::vector<Item>& items) {
+// Uploads a kernel's items (largest first) for a grid of g workgroups, each
+// taking every g-th item: every other round of g items is reversed, so the
+// workgroup that takes a round's largest item takes the next round's
+// smallest and the workgroups' totals stay close.
+hipError_t upload_list(Item** d, int* count, std::vector<Item> items, int g) {
     if (*d) hipFree(*d);
     *d = nullptr;
     *count = (int)items.size();
     if (items.empty()) return hipSuccess;
+    g = std::max(1, std::min(g, (int)items.size()));
+    for (size_t r0 = g; r0 < items.size(); r0 += 2 * (size_t)g)
+        std::reverse(items.begin() + r0, items.begin() + std::min(items.size(), r0 + g));
     hipError_t e = hipMalloc(d, items.size() * sizeof(Item));
     if (e == hipSuccess)
         e = hipMemcpy(*d, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice);
@@ -464,9 +480,9 @@ hipError_t upload_items(ao_batch* b, const std::vector<Item>& items) {
             b->launches = std::max(b->launches, P);
         }
     }
-    hipError_t e = upload_list(&b->d_items, &b->nitems, single);
-    if (e == hipSuccess) e = upload_list(&b->d_items_f, &b->nitems_f, fused);
-    if (e == hipSuccess) e = upload_list(&b->d_items_3, &b->nitems_3, tri);
+    hipError_t e = upload_list(&b->d_items, &b->nitems, std::move(single), b->grid);
+    if (e == hipSuccess) e = upload_list(&b->d_items_f, &b->nitems_f, std::move(fused), b->grid_f);
+    if (e == hipSuccess) e = upload_list(&b->d_items_3, &b->nitems_3, std::move(tri), b->grid_3);
     return e;
 }
 
